@@ -1,0 +1,157 @@
+/*
+ * nnef.h - C ABI of libnnef: multiplicative-update (MU) sweeps for nonnegative
+ * einsum factorizations on AMD Instinct MI355X (gfx950).
+ *
+ * The method is NNEinFact (Hood and Schein, "Near-Universal Multiplicative
+ * Updates for Nonnegative Einsum Factorization"):
+ *   - a model is an einsum string  i_1 r_1, ..., i_L r_L -> i_1 ... i_M
+ *     (Sec. 2, eqs. 2.1-2.3): letters on the right are the observed modes of
+ *     the data tensor Y, letters only on the left are contracted;
+ *   - one sweep is the inner loop of Algorithm 1 (Sec. 3): for l = 1..L,
+ *     rebuild Yhat, form the numerator and denominator einsums einstr_l with
+ *     a(Y, Yhat) and b(Y, Yhat), and set
+ *     Theta^(l) <- max(eps, Theta^(l) * g^{-1}(N_l / D_l))  (eq. 3.4);
+ *   - the loss is the (alpha, beta)-divergence of App. B, in the paper's
+ *     convention: KL = (1, 0), squared Euclidean = (1, 1), Itakura-Saito =
+ *     (1, -1);
+ *   - missing data are a binary mask (Sec. 6, "Experimental design"); the
+ *     weights a, b are multiplied by the mask, so missing entries of Y are
+ *     never read into arithmetic and may hold any bit pattern (NaN included).
+ *
+ * Memory and streams
+ *   All tensor arguments are DEVICE pointers owned by the caller; the library
+ *   never frees or reallocates them.  Layouts are dense row-major:
+ *     Y, mask : axes in the order of the output letters of the model string;
+ *     factor l: axes in the order of operand l's subscripts.
+ *   Y is float32; mask is uint8 with 1 = observed, 0 = missing (NULL = fully
+ *   observed).  Factors are float32 and are updated in place.
+ *   `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Entry points only enqueue work on that stream, except where a comment
+ *   says the call synchronises.  Calls that share a plan must not overlap:
+ *   a plan owns one workspace.
+ *
+ * Errors
+ *   Every entry point returns an nnef_status and never aborts.  A non-OK
+ *   status leaves a message for nnef_last_error() (thread-local).  A status
+ *   returned after work was enqueued (NNEF_E_DEVICE) means the stream's
+ *   contents are undefined.
+ */
+#ifndef NNEF_H
+#define NNEF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnef_plan_s* nnef_plan_t;
+
+typedef enum {
+  NNEF_OK = 0,
+  NNEF_E_PARSE = 1,            /* malformed model string                        */
+  NNEF_E_SHAPE = 2,            /* sizes <= 0, count mismatch, tensor too large  */
+  NNEF_E_LOSS_UNSUPPORTED = 3, /* alpha = 0 with beta != 1, or non-finite       */
+  NNEF_E_ARG = 4,              /* NULL pointer, bad option, bad sweep count     */
+  NNEF_E_DEVICE = 5,           /* a HIP call failed                             */
+  NNEF_E_NOMEM = 6,            /* device workspace allocation failed            */
+  NNEF_E_UNSUPPORTED = 7       /* a model the planner cannot lower              */
+} nnef_status;
+
+/* Input precision of the MFMA contractions.  Weights, ratios, powers, the
+ * update and the loss terms are always float32; loss sums are float64. */
+typedef enum { NNEF_FP32 = 0, NNEF_BF16 = 1, NNEF_FP16 = 2 } nnef_prec;
+
+typedef struct {
+  double eps;          /* floor of eq. 3.1; default 1e-10                        */
+  int    prec;         /* nnef_prec; default NNEF_FP32                           */
+  int    deterministic;/* 1 (default): fixed-order reductions, bitwise repeatable */
+  int    reserved[6];  /* must be zero                                           */
+} nnef_options;
+
+/* Fill *opt with the defaults. */
+void nnef_default_options(nnef_options* opt);
+
+/*
+ * nnef_plan - parse and lower a model string; allocate the plan's workspace.
+ *   model_str : e.g. "ir,jr,kr->ijk" or "ia,jab,kbc,lc->ijkl" (eq. 2.2).
+ *   mode_sizes: n_modes sizes, in the order of the output letters.
+ *   ranks     : n_ranks sizes of the contracted letters, in order of their
+ *               first appearance on the left-hand side.
+ *   alpha,beta: the (alpha, beta)-divergence of App. B.
+ *   opt       : NULL for defaults.
+ *   out       : receives the plan; free it with nnef_plan_destroy.
+ * Rejects (status, nothing allocated):
+ *   NNEF_E_PARSE  missing or repeated "->", a non-letter, an empty operand,
+ *                 a letter repeated inside one operand or in the output, an
+ *                 output letter used by no operand;
+ *   NNEF_E_SHAPE  n_modes / n_ranks not matching the string, a size <= 0,
+ *                 2^31 or more data entries;
+ *   NNEF_E_LOSS_UNSUPPORTED  alpha = 0 with beta != 1 (App. B gives no
+ *                 decomposition), non-finite alpha or beta;
+ *   NNEF_E_UNSUPPORTED  a block whose contraction width exceeds 64 in every
+ *                 lowering the planner knows.
+ * Synchronises the device once (workspace set-up).
+ */
+nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_modes,
+                      const int64_t* ranks, int n_ranks, double alpha, double beta,
+                      const nnef_options* opt, nnef_plan_t* out);
+
+void nnef_plan_destroy(nnef_plan_t plan);
+
+/* Number of factors L, and the number of elements of factor l (0-based). */
+int     nnef_plan_num_factors(nnef_plan_t plan);
+int64_t nnef_plan_factor_numel(nnef_plan_t plan, int l);
+
+/*
+ * Human-readable description of the lowering chosen for every block
+ * (split of the observed modes, contraction width, side operands, chain-back).
+ * Returns the number of characters the full text needs (excluding the
+ * terminator) and copies at most buf_len - 1 of them.
+ */
+size_t nnef_plan_describe(nnef_plan_t plan, char* buf, size_t buf_len);
+
+/*
+ * nnef_step - run n_sweeps sweeps of Algorithm 1 (Sec. 3) in place.
+ *   factors   : host array of L device pointers (float32, layouts above).
+ *   loss_trace: NULL, or a device array of n_sweeps doubles; entry s receives
+ *               the masked loss sum_{observed} D(y, yhat) of the state at the
+ *               START of sweep s (computed during that sweep's first block).
+ * Enqueue only; no host synchronisation.  n_sweeps = 0 is a no-op.
+ */
+nnef_status nnef_step(nnef_plan_t plan, const float* Y, const uint8_t* mask,
+                      float* const* factors, int n_sweeps, double* loss_trace,
+                      void* stream);
+
+/*
+ * nnef_loss - masked loss sum_{observed} D_{alpha,beta}(y, yhat) (eq. 3.1,
+ * App. B) of the given factors, reduced in float64.  Writes *loss_out (host).
+ * Synchronises `stream`.
+ */
+nnef_status nnef_loss(nnef_plan_t plan, const float* Y, const uint8_t* mask,
+                      const float* const* factors, double* loss_out, void* stream);
+
+/* As nnef_loss, but writes the double to device memory and does not sync. */
+nnef_status nnef_loss_device(nnef_plan_t plan, const float* Y, const uint8_t* mask,
+                             const float* const* factors, double* d_loss_out,
+                             void* stream);
+
+/*
+ * Kernel timing for measurement tools.  While enabled, nnef_step records a
+ * hipEvent pair on `stream` around every fused pass (the pass over Y of each
+ * block update).  nnef_plan_timing synchronises on those events and returns
+ * the number of timed passes and their total duration in milliseconds, then
+ * forgets them.  Disabled by default; enabling it adds two event records per
+ * block update.
+ */
+nnef_status nnef_plan_set_timing(nnef_plan_t plan, int enable);
+nnef_status nnef_plan_timing(nnef_plan_t plan, int* n_passes, double* total_ms);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* nnef_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNEF_H */

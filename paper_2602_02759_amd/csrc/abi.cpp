@@ -1,0 +1,472 @@
+// C ABI of libnnef (declared in include/nnef.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nnef.h"
+#include "planner.hpp"
+
+using namespace nnef;
+
+namespace {
+thread_local std::string g_last_error;
+
+nnef_status fail(nnef_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+nnef_status hip_fail(int e, const char* what) {
+  return fail(NNEF_E_DEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)e));
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+}  // namespace
+
+struct nnef_plan_s {
+  Model m;
+  LossSpec ls;
+  nnef_options opt;
+  std::vector<BlockPlan> blocks;
+  std::vector<int64_t> ws_sizes;   // floats per workspace buffer
+  std::vector<float*> ws;
+  void* ws_base = nullptr;
+  std::vector<void*> tables;       // device index tables
+  float* partN = nullptr;
+  float* partD = nullptr;
+  double* loss_part = nullptr;
+  double* loss_tmp = nullptr;
+  float* dcol = nullptr;
+  int max_wg = 0;
+  std::vector<int64_t> numel;
+  std::string description;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+
+extern "C" {
+
+void nnef_default_options(nnef_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps = 1e-10;
+  o->prec = NNEF_FP32;
+  o->deterministic = 1;
+}
+
+const char* nnef_last_error(void) { return g_last_error.c_str(); }
+
+static void drop_events(nnef_plan_s* p) {
+  for (auto& e : p->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p->events.clear();
+}
+
+static void free_plan(nnef_plan_s* p) {
+  if (!p) return;
+  drop_events(p);
+  if (p->ws_base) (void)hipFree(p->ws_base);
+  for (void* t : p->tables) (void)hipFree(t);
+  if (p->partN) (void)hipFree(p->partN);
+  if (p->partD) (void)hipFree(p->partD);
+  if (p->loss_part) (void)hipFree(p->loss_part);
+  if (p->loss_tmp) (void)hipFree(p->loss_tmp);
+  if (p->dcol) (void)hipFree(p->dcol);
+  delete p;
+}
+
+void nnef_plan_destroy(nnef_plan_t p) { free_plan(p); }
+
+int nnef_plan_num_factors(nnef_plan_t p) { return p ? (int)p->m.ops.size() : 0; }
+
+int64_t nnef_plan_factor_numel(nnef_plan_t p, int l) {
+  if (!p || l < 0 || l >= (int)p->numel.size()) return -1;
+  return p->numel[l];
+}
+
+size_t nnef_plan_describe(nnef_plan_t p, char* buf, size_t n) {
+  if (!p) return 0;
+  const std::string& s = p->description;
+  if (buf && n) {
+    const size_t k = std::min(n - 1, s.size());
+    std::memcpy(buf, s.data(), k);
+    buf[k] = 0;
+  }
+  return s.size();
+}
+
+static nnef_status upload_table(nnef_plan_s* p, const std::vector<uint32_t>& t, uint32_t** out) {
+  void* d = nullptr;
+  const size_t bytes = std::max<size_t>(4, t.size() * 4);
+  if (hipMalloc(&d, bytes) != hipSuccess) return fail(NNEF_E_NOMEM, "hipMalloc of an index table failed");
+  p->tables.push_back(d);
+  if (!t.empty() && hipMemcpy(d, t.data(), t.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(NNEF_E_DEVICE, "copy of an index table failed");
+  *out = (uint32_t*)d;
+  return NNEF_OK;
+}
+
+nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_modes,
+                      const int64_t* ranks, int n_ranks, double alpha, double beta,
+                      const nnef_options* opt, nnef_plan_t* out) {
+  if (!model_str || !out) return fail(NNEF_E_ARG, "model_str and out must not be NULL");
+  *out = nullptr;
+  auto* p = new nnef_plan_s();
+  nnef_default_options(&p->opt);
+  if (opt) {
+    p->opt = *opt;
+    if (!(p->opt.eps > 0) || !std::isfinite(p->opt.eps)) {
+      free_plan(p);
+      return fail(NNEF_E_ARG, "eps must be a positive finite number");
+    }
+    if (p->opt.prec != NNEF_FP32) {
+      free_plan(p);
+      return fail(NNEF_E_ARG, "only NNEF_FP32 contractions are available in this build");
+    }
+  }
+  std::string err;
+  if (parse_model(model_str, p->m, err) != ST_OK) {
+    free_plan(p);
+    return fail(NNEF_E_PARSE, err);
+  }
+  Model& m = p->m;
+  if (n_modes != (int)m.out.size() || n_ranks != (int)m.latent.size() ||
+      (n_modes && !mode_sizes) || (n_ranks && !ranks)) {
+    free_plan(p);
+    return fail(NNEF_E_SHAPE, "model string has " + std::to_string(m.out.size()) + " modes and " +
+                                  std::to_string(m.latent.size()) + " contracted letters");
+  }
+  int64_t N = 1;
+  for (int i = 0; i < n_modes; ++i) {
+    if (mode_sizes[i] <= 0) {
+      free_plan(p);
+      return fail(NNEF_E_SHAPE, "mode sizes must be positive");
+    }
+    m.size[(unsigned char)m.out[i]] = mode_sizes[i];
+    N *= mode_sizes[i];
+    if (N >= (int64_t(1) << 31)) {
+      free_plan(p);
+      return fail(NNEF_E_SHAPE, "the data tensor must have fewer than 2^31 entries");
+    }
+  }
+  for (int i = 0; i < n_ranks; ++i) {
+    if (ranks[i] <= 0) {
+      free_plan(p);
+      return fail(NNEF_E_SHAPE, "ranks must be positive");
+    }
+    m.size[(unsigned char)m.latent[i]] = ranks[i];
+  }
+  if (make_loss(alpha, beta, p->ls, err) != ST_OK) {
+    free_plan(p);
+    return fail(NNEF_E_LOSS_UNSUPPORTED, err);
+  }
+  for (auto& t : m.ops) {
+    int64_t n = 1;
+    for (char c : t) n *= m.size[(unsigned char)c];
+    p->numel.push_back(n);
+  }
+  // ---- lowering of every block
+  const int target_wg = env_int("NNEF_TARGET_WG", 512);
+  size_t part_elems = 0;
+  for (int l = 0; l < (int)m.ops.size(); ++l) {
+    BlockPlan bp;
+    Status st = lower_block(m, l, bp, p->ws_sizes, err);
+    if (st != ST_OK) {
+      free_plan(p);
+      return fail(st == ST_UNSUPPORTED ? NNEF_E_UNSUPPORTED : NNEF_E_SHAPE, err);
+    }
+    if (!choose_geometry(m, bp, target_wg)) {
+      free_plan(p);
+      return fail(NNEF_E_SHAPE, "grid too large");
+    }
+    part_elems = std::max(part_elems, (size_t)bp.n_chunks * bp.nP * bp.KP);
+    p->max_wg = std::max(p->max_wg, bp.n_wg);
+    p->blocks.push_back(bp);
+  }
+  // ---- device memory
+  size_t ws_total = 0;
+  for (auto s : p->ws_sizes) ws_total += (size_t)((s + 63) / 64 * 64);
+  if (ws_total) {
+    if (hipMalloc(&p->ws_base, ws_total * sizeof(float)) != hipSuccess) {
+      free_plan(p);
+      return fail(NNEF_E_NOMEM, "workspace allocation failed");
+    }
+    if (hipMemset(p->ws_base, 0, ws_total * sizeof(float)) != hipSuccess) {
+      free_plan(p);
+      return fail(NNEF_E_DEVICE, "workspace clear failed");
+    }
+  }
+  size_t off = 0;
+  for (auto s : p->ws_sizes) {
+    p->ws.push_back((float*)p->ws_base + off);
+    off += (size_t)((s + 63) / 64 * 64);
+  }
+  if (hipMalloc((void**)&p->partN, std::max<size_t>(1, part_elems) * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&p->partD, std::max<size_t>(1, part_elems) * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&p->loss_part, std::max(1, p->max_wg) * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->loss_tmp, sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->dcol, 64 * sizeof(float)) != hipSuccess) {
+    free_plan(p);
+    return fail(NNEF_E_NOMEM, "partial-sum allocation failed");
+  }
+  for (auto& bp : p->blocks) {
+    nnef_status st = upload_table(p, offsets_table(m, bp.P), &bp.d_poff);
+    if (st == NNEF_OK) st = upload_table(p, offsets_table(m, bp.Q), &bp.d_qoff);
+    for (size_t i = 0; st == NNEF_OK && i < bp.pieces.size(); ++i) {
+      Piece& pc = bp.pieces[i];
+      if (pc.factor >= 0 && !piece_is_identity(m, bp.Q, pc.obs))
+        st = upload_table(p, piece_rows_table(m, bp.Q, pc.obs), &bp.d_pidx[i]);
+    }
+    if (st == NNEF_OK && bp.ones_buf >= 0) {
+      const float one = 1.0f;
+      if (hipMemcpy(p->ws[bp.ones_buf], &one, sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        st = fail(NNEF_E_DEVICE, "workspace init failed");
+    }
+    if (st != NNEF_OK) {
+      free_plan(p);
+      return st;
+    }
+    p->description += describe_block(m, bp) + "\n";
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    free_plan(p);
+    return fail(NNEF_E_DEVICE, "device synchronisation failed after plan set-up");
+  }
+  *out = p;
+  return NNEF_OK;
+}
+
+// ---------------------------------------------------------------------------
+static const float* tensor_ptr(const nnef_plan_s* p, const BlockPlan& bp, const TensorRef& t,
+                               const float* const* factors) {
+  switch (t.kind) {
+    case TK_FACTOR: return factors[t.id];
+    case TK_WS: return p->ws[t.id];
+    case TK_NL: return p->ws[bp.NL_buf];
+    default: return p->ws[bp.DL_buf];
+  }
+}
+
+static int run_program(const nnef_plan_s* p, const BlockPlan& bp, const std::vector<Step>& prog,
+                       const float* const* factors, hipStream_t s) {
+  const Model& m = p->m;
+  for (const Step& st : prog) {
+    EinsumArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_in = (int)st.in.size();
+    a.n_out = (int)st.out.subs.size();
+    a.n_sum = (int)st.sum.size();
+    a.n_out_total = 1;
+    for (int d = 0; d < a.n_out; ++d) {
+      const char c = st.out.subs[d];
+      a.out_size[d] = m.size[(unsigned char)c];
+      a.out_stride[d] = st.out.strides[d];
+      a.n_out_total *= a.out_size[d];
+    }
+    for (int d = 0; d < a.n_sum; ++d) a.sum_size[d] = m.size[(unsigned char)st.sum[d]];
+    for (int i = 0; i < a.n_in; ++i) {
+      const TensorRef& t = st.in[i];
+      a.in[i] = tensor_ptr(p, bp, t, factors);
+      for (int d = 0; d < a.n_out; ++d) {
+        const size_t pos = t.subs.find(st.out.subs[d]);
+        a.in_out_stride[i][d] = pos == std::string::npos ? 0 : t.strides[pos];
+      }
+      for (int d = 0; d < a.n_sum; ++d) {
+        const size_t pos = t.subs.find(st.sum[d]);
+        a.in_sum_stride[i][d] = pos == std::string::npos ? 0 : t.strides[pos];
+      }
+    }
+    a.out = const_cast<float*>(tensor_ptr(p, bp, st.out, factors));
+    const int e = launch_einsum(a, s);
+    if (e) return e;
+  }
+  return 0;
+}
+
+static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const float* Y,
+                            const uint8_t* M, const float* const* factors) {
+  FusedArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.Y = Y;
+  a.M = M;
+  a.p_off = bp.d_poff;
+  a.q_off = bp.d_qoff;
+  a.L = bp.L_direct ? factors[bp.ell] : p->ws[bp.L_buf];
+  a.ldL = bp.ldL;
+  a.K = bp.K;
+  a.nP = (int)bp.nP;
+  a.nQ = (int)bp.nQ;
+  a.npieces = (int)bp.pieces.size();
+  for (int i = 0; i < a.npieces; ++i) {
+    const Piece& pc = bp.pieces[i];
+    a.piece[i] = pc.factor >= 0 ? factors[pc.factor] : p->ws[pc.ws];
+    a.pidx[i] = bp.d_pidx[i];
+    a.ldpiece[i] = pc.ld;
+  }
+  a.n_panels = bp.n_panels;
+  a.q_per_wave = bp.q_per_wave;
+  a.n_chunks = bp.n_chunks;
+  a.n_wg = bp.n_wg;
+  a.xcd_remap = bp.xcd_remap;
+  a.partN = p->partN;
+  a.partD = p->partD;
+  a.no_d = (p->ls.b_is_one() && M == nullptr) ? 1 : 0;
+  a.alpha = (float)p->ls.alpha;
+  a.beta = (float)p->ls.beta;
+  const double ab = p->ls.alpha * p->ls.beta, apb = p->ls.alpha + p->ls.beta;
+  a.ab_inv = ab != 0 ? (float)(1.0 / ab) : 0.f;
+  a.apb_inv = apb != 0 ? (float)(1.0 / apb) : 0.f;
+  a.lk = p->ls.lk;
+  return a;
+}
+
+static int run_side_prep(const nnef_plan_s* p, const BlockPlan& bp, const float* const* factors,
+                         hipStream_t s) {
+  int e = run_program(p, bp, bp.L_prog, factors, s);
+  if (!e) e = run_program(p, bp, bp.R_prog, factors, s);
+  return e;
+}
+
+nnef_status nnef_step(nnef_plan_t p, const float* Y, const uint8_t* M, float* const* factors,
+                      int n_sweeps, double* loss_trace, void* stream) {
+  if (!p || !Y || !factors) return fail(NNEF_E_ARG, "plan, Y and factors must not be NULL");
+  if (n_sweeps < 0) return fail(NNEF_E_ARG, "n_sweeps must be >= 0");
+  const int L = (int)p->m.ops.size();
+  for (int l = 0; l < L; ++l)
+    if (!factors[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const float* const* cf = factors;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    for (int l = 0; l < L; ++l) {
+      const BlockPlan& bp = p->blocks[l];
+      int e = run_side_prep(p, bp, cf, s);
+      if (e) return hip_fail(e, "side-operand contraction launch");
+      FusedArgs fa = fused_args(p, bp, Y, M, cf);
+      const bool want_loss = loss_trace && l == 0;
+      fa.loss_part = want_loss ? p->loss_part : nullptr;
+      hipEvent_t ev0 = nullptr, ev1 = nullptr;
+      if (p->timing) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess ||
+            hipEventRecord(ev0, s) != hipSuccess)
+          return fail(NNEF_E_DEVICE, "timing event set-up failed");
+      }
+      e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, s);
+      if (e) return hip_fail(e, "fused pass launch");
+      if (p->timing) {
+        if (hipEventRecord(ev1, s) != hipSuccess) return fail(NNEF_E_DEVICE, "timing event record failed");
+        p->events.emplace_back(ev0, ev1);
+      }
+      UpdateArgs ua;
+      std::memset(&ua, 0, sizeof(ua));
+      ua.partN = p->partN;
+      ua.partD = p->partD;
+      ua.n_chunks = bp.n_chunks;
+      ua.nP = (int)bp.nP;
+      ua.K = bp.K;
+      ua.KP = bp.KP;
+      ua.no_d = fa.no_d;
+      ua.npieces = fa.npieces;
+      for (int i = 0; i < fa.npieces; ++i) {
+        ua.piece[i] = fa.piece[i];
+        ua.ldpiece[i] = fa.ldpiece[i];
+        ua.nrows[i] = bp.pieces[i].nrows;
+      }
+      ua.theta = bp.L_direct ? factors[l] : nullptr;
+      ua.ldT = bp.ldL;
+      ua.NL = bp.L_direct ? nullptr : p->ws[bp.NL_buf];
+      ua.DL = bp.L_direct ? nullptr : p->ws[bp.DL_buf];
+      ua.upd = p->ls.upd;
+      ua.gamma = (float)p->ls.gamma;
+      ua.eps = (float)p->opt.eps;
+      if (want_loss) {
+        ua.loss_part = p->loss_part;
+        ua.n_loss_part = bp.n_wg;
+        ua.loss_out = loss_trace + sw;
+      }
+      e = launch_update(ua, p->dcol, s);
+      if (e) return hip_fail(e, "update launch");
+      if (!bp.L_direct) {
+        e = run_program(p, bp, bp.chainN, cf, s);
+        if (!e) e = run_program(p, bp, bp.chainD, cf, s);
+        if (e) return hip_fail(e, "chain-back contraction launch");
+        ApplyArgs aa;
+        aa.theta = factors[l];
+        aa.N = p->ws[bp.Nl_buf];
+        aa.D = p->ws[bp.Dl_buf];
+        aa.n = p->numel[l];
+        aa.upd = p->ls.upd;
+        aa.gamma = (float)p->ls.gamma;
+        aa.eps = (float)p->opt.eps;
+        e = launch_apply(aa, s);
+        if (e) return hip_fail(e, "update launch");
+      }
+    }
+  }
+  return NNEF_OK;
+}
+
+nnef_status nnef_plan_set_timing(nnef_plan_t p, int enable) {
+  if (!p) return fail(NNEF_E_ARG, "plan must not be NULL");
+  p->timing = enable != 0;
+  if (!p->timing) drop_events(p);
+  return NNEF_OK;
+}
+
+nnef_status nnef_plan_timing(nnef_plan_t p, int* n_passes, double* total_ms) {
+  if (!p || !n_passes || !total_ms) return fail(NNEF_E_ARG, "NULL argument");
+  double tot = 0.0;
+  for (auto& e : p->events) {
+    if (hipEventSynchronize(e.second) != hipSuccess) return fail(NNEF_E_DEVICE, "event sync failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess)
+      return fail(NNEF_E_DEVICE, "event timing failed");
+    tot += ms;
+  }
+  *n_passes = (int)p->events.size();
+  *total_ms = tot;
+  drop_events(p);
+  return NNEF_OK;
+}
+
+nnef_status nnef_loss_device(nnef_plan_t p, const float* Y, const uint8_t* M,
+                             const float* const* factors, double* d_loss, void* stream) {
+  if (!p || !Y || !factors || !d_loss) return fail(NNEF_E_ARG, "NULL argument");
+  for (int l = 0; l < (int)p->m.ops.size(); ++l)
+    if (!factors[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const BlockPlan& bp = p->blocks[0];
+  int e = run_side_prep(p, bp, factors, s);
+  if (e) return hip_fail(e, "side-operand contraction launch");
+  FusedArgs fa = fused_args(p, bp, Y, M, factors);
+  fa.loss_only = 1;
+  fa.loss_part = p->loss_part;
+  e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, s);
+  if (e) return hip_fail(e, "loss pass launch");
+  e = launch_loss_final(p->loss_part, bp.n_wg, d_loss, s);
+  if (e) return hip_fail(e, "loss reduction launch");
+  return NNEF_OK;
+}
+
+nnef_status nnef_loss(nnef_plan_t p, const float* Y, const uint8_t* M, const float* const* factors,
+                      double* loss_out, void* stream) {
+  if (!loss_out) return fail(NNEF_E_ARG, "loss_out must not be NULL");
+  nnef_status st = nnef_loss_device(p, Y, M, factors, p ? p->loss_tmp : nullptr, stream);
+  if (st != NNEF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(loss_out, p->loss_tmp, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "loss copy");
+  return NNEF_OK;
+}
+
+}  // extern "C"

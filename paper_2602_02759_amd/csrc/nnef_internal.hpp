@@ -1,0 +1,123 @@
+// Internal declarations shared by the planner (host C++) and the kernels (HIP).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace nnef {
+
+constexpr int kMaxPieces = 3;     // factors multiplied together to form one side row
+constexpr int kMaxEinsumIn = 4;   // inputs of one einsum step
+constexpr int kMaxEinsumLetters = 10;
+
+// Weight functions a, b (App. B), specialised by (alpha, beta).
+enum WeightKind : int {
+  WK_KL = 0,    // (1, 0):   a = y/yh,              b = 1
+  WK_EUC = 1,   // (1, 1):   a = y,                 b = yh
+  WK_SQRT = 2,  // (.5, 1):  a = sqrt(y),           b = sqrt(yh)
+  WK_IS = 3,    // (1, -1):  a = y/yh^2,            b = 1/yh
+  WK_GEN = 4,   // alpha!=0: a = y^al yh^(be-1),    b = yh^(al+be-1)
+  WK_RKL = 5,   // (0, 1):   a = log(y/yh),         b = 1
+  WK_COUNT = 6
+};
+
+// g^{-1} of App. B: r^gamma with the exponent specialised, or exp(r).
+enum UpdateKind : int { UP_ONE = 0, UP_SQR = 1, UP_SQRT = 2, UP_POW = 3, UP_EXP = 4 };
+
+// Case of the (alpha, beta)-divergence definition (App. B), plus closed forms.
+enum LossKind : int {
+  LK_GENERIC = 0, LK_BETA0 = 1, LK_AMB = 2, LK_ALPHA0 = 3, LK_ZERO = 4,
+  LK_KL = 5, LK_EUC = 6, LK_IS = 7, LK_SQRT = 8
+};
+
+struct LossSpec {
+  double alpha = 1, beta = 0, gamma = 1;
+  int wk = WK_KL, upd = UP_ONE, lk = LK_KL;
+  bool b_is_one() const { return wk == WK_KL || wk == WK_RKL; }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks (plain data, passed by value).
+// ---------------------------------------------------------------------------
+// Fused pass: for a split of the observed modes into P (rows) and Q (columns),
+//   yhat[p,q] = sum_k L[p,k] R[q,k]          (R[q,k] = prod_m piece_m[idx_m[q],k])
+//   Wa = m * a(y, yhat), Wb = m * b(y, yhat)
+//   N[p,k] = sum_q Wa[p,q] R[q,k],  D[p,k] = sum_q Wb[p,q] R[q,k]
+// One workgroup = 4 waves on one panel of rows and 4 consecutive q ranges; it
+// writes one partial N, D of shape [nP][KP] at slot (q chunk).
+struct FusedArgs {
+  const float* Y;
+  const uint8_t* M;            // nullptr: fully observed
+  const uint32_t* p_off;       // [nP] element offset of row p in Y
+  const uint32_t* q_off;       // [nQ] element offset of column q in Y
+  const float* L;              // L[p*ldL + k], k < K
+  int ldL;
+  int K;                       // true contraction width (<= KP)
+  int nP, nQ;
+  int npieces;
+  const float* piece[kMaxPieces];
+  const uint32_t* pidx[kMaxPieces];   // row index of column q in piece m; nullptr = q
+  int ldpiece[kMaxPieces];
+  int n_panels;                // ceil(nP / rows per wave)
+  int q_per_wave;              // multiple of 16
+  int n_chunks;                // q chunks = partial slots
+  int n_wg;                    // grid size
+  int xcd_remap;               // 1: spread consecutive work over one XCD's slots
+  float* partN;                // [n_chunks][nP][KP]
+  float* partD;                // [n_chunks][nP][KP] (unused when no_d)
+  double* loss_part;           // [n_wg] or nullptr
+  int no_d;                    // D is a closed form (b = 1, no mask): skip it
+  int loss_only;               // only the loss is wanted
+  float alpha, beta;           // for WK_GEN and the generic loss
+  float ab_inv, apb_inv;       // 1/(alpha*beta), 1/(alpha+beta) (generic loss)
+  int lk;                      // LossKind
+};
+
+// Reduce the partials of a fused pass and apply the update (or store N_L/D_L).
+struct UpdateArgs {
+  const float* partN; const float* partD;
+  int n_chunks, nP, K, KP;
+  int no_d;
+  // closed-form D (no_d): D[p,k] = prod_m colsum(piece_m)[k]
+  int npieces;
+  const float* piece[kMaxPieces];
+  int ldpiece[kMaxPieces];
+  int64_t nrows[kMaxPieces];
+  // direct update target (theta = L itself) or N_L/D_L output
+  float* theta; int ldT;       // theta[p*ldT + k]
+  float* NL; float* DL;        // [nP][K] when chaining back (theta == nullptr)
+  int upd; float gamma; float eps;
+  // loss finalisation (first block of a sweep)
+  const double* loss_part; int n_loss_part; double* loss_out;
+};
+
+// Generic n-ary contraction out[o] = sum_c prod_i in_i[...] over explicit strides.
+struct EinsumArgs {
+  int n_in;
+  const float* in[kMaxEinsumIn];
+  int n_out;                                   // number of output letters
+  int n_sum;                                   // number of summed letters
+  int64_t out_size[kMaxEinsumLetters];
+  int64_t out_stride[kMaxEinsumLetters];       // output strides (elements)
+  int64_t sum_size[kMaxEinsumLetters];
+  int64_t in_out_stride[kMaxEinsumIn][kMaxEinsumLetters];
+  int64_t in_sum_stride[kMaxEinsumIn][kMaxEinsumLetters];
+  int64_t n_out_total;
+  float* out;
+};
+
+// Elementwise update from full-size N, D (after a chain-back).
+struct ApplyArgs {
+  float* theta; const float* N; const float* D; int64_t n;
+  int upd; float gamma; float eps;
+};
+
+// Launchers (kernels.hip).  Return 0 or a hipError_t value.
+int launch_fused(const FusedArgs& a, int KP, int wk, bool vecq, void* stream);
+int launch_update(const UpdateArgs& a, float* dcol, void* stream);  // dcol: [K] scratch for a closed-form D
+int launch_einsum(const EinsumArgs& a, void* stream);
+int launch_apply(const ApplyArgs& a, void* stream);
+int launch_loss_final(const double* part, int n, double* out, void* stream);
+int launch_zero(float* p, int64_t n, void* stream);
+
+}  // namespace nnef

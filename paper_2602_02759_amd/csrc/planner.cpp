@@ -1,0 +1,533 @@
+// Host planner of libnnef: parse the model string, choose the loss case, and
+// lower every block update of Algorithm 1 to the fused pass.
+//
+// Lowering of block l.  Split the observed modes into P (containing the modes
+// of operand l) and Q, with every operand's observed modes entirely on one
+// side; operands without observed modes go to either side.  With kappa the
+// contracted letters used on both sides,
+//   yhat[p, q] = sum_kappa L[p, kappa] R[q, kappa]                      (eq. 2.1)
+// where L (R) contracts the P-side (Q-side) operands over their other
+// letters.  The numerator of eq. 3.6 for operand l factors through L:
+//   N_L[p, kappa] = sum_q a(y, yhat)[p, q] R[q, kappa],
+//   N_l = einsum(P-side operands except l, N_L -> subscripts of l),
+// the last step ("chain-back") being the P-side part of einstr_l.  When l is
+// the only P-side operand and is laid out as [P modes, kappa], N_l = N_L.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <sstream>
+#include <stdexcept>
+
+#include "planner.hpp"
+
+namespace nnef {
+
+static bool is_letter(char c) { return (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z'); }
+
+// ---------------------------------------------------------------------------
+// Model strings (Sec. 2, eq. 2.2)
+// ---------------------------------------------------------------------------
+Status parse_model(const std::string& s_in, Model& m, std::string& err) {
+  std::string s;
+  for (char c : s_in)
+    if (c != ' ') s.push_back(c);
+  const size_t arrow = s.find("->");
+  if (arrow == std::string::npos || s.find("->", arrow + 2) != std::string::npos) {
+    err = "model string needs exactly one '->'";
+    return ST_PARSE;
+  }
+  std::string lhs = s.substr(0, arrow);
+  m.out = s.substr(arrow + 2);
+  m.ops.clear();
+  std::string cur;
+  for (size_t i = 0; i <= lhs.size(); ++i) {
+    if (i == lhs.size() || lhs[i] == ',') {
+      if (cur.empty()) {
+        err = "empty operand in model string";
+        return ST_PARSE;
+      }
+      m.ops.push_back(cur);
+      cur.clear();
+    } else {
+      cur.push_back(lhs[i]);
+    }
+  }
+  std::vector<std::string> all = m.ops;
+  all.push_back(m.out);
+  for (const auto& t : all) {
+    std::set<char> seen;
+    for (char c : t) {
+      if (!is_letter(c)) {
+        err = std::string("bad subscript character '") + c + "'";
+        return ST_PARSE;
+      }
+      if (!seen.insert(c).second) {
+        err = "letter '" + std::string(1, c) + "' repeated in '" + t + "'";
+        return ST_PARSE;
+      }
+    }
+  }
+  for (char c : m.out) {
+    bool used = false;
+    for (const auto& t : m.ops) used |= t.find(c) != std::string::npos;
+    if (!used) {
+      err = "output letter '" + std::string(1, c) + "' appears in no operand";
+      return ST_PARSE;
+    }
+  }
+  m.latent.clear();
+  for (const auto& t : m.ops)
+    for (char c : t)
+      if (m.out.find(c) == std::string::npos && m.latent.find(c) == std::string::npos)
+        m.latent.push_back(c);
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// (alpha, beta) -> weights, update exponent, loss case (App. B)
+// ---------------------------------------------------------------------------
+Status make_loss(double al, double be, LossSpec& ls, std::string& err) {
+  if (!std::isfinite(al) || !std::isfinite(be)) {
+    err = "alpha and beta must be finite";
+    return ST_LOSS;
+  }
+  ls.alpha = al;
+  ls.beta = be;
+  if (al == 0.0) {
+    if (be != 1.0) {
+      err = "alpha = 0 with beta != 1 has no multiplicative update (App. B)";
+      return ST_LOSS;
+    }
+    ls.wk = WK_RKL;
+    ls.upd = UP_EXP;
+    ls.gamma = 1.0;
+    ls.lk = LK_ALPHA0;
+    return ST_OK;
+  }
+  // g(lambda) of App. B with rho = (1 - beta)/alpha; g^{-1}(r) = r^gamma
+  const double rho = (1.0 - be) / al;
+  if (rho > 1.0) ls.gamma = 1.0 / (1.0 - be);
+  else if (rho < 0.0) ls.gamma = 1.0 / (al + be - 1.0);
+  else ls.gamma = 1.0 / al;
+  ls.upd = ls.gamma == 1.0 ? UP_ONE : ls.gamma == 2.0 ? UP_SQR : ls.gamma == 0.5 ? UP_SQRT : UP_POW;
+  if (al == 1.0 && be == 0.0) ls.wk = WK_KL;
+  else if (al == 1.0 && be == 1.0) ls.wk = WK_EUC;
+  else if (al == 0.5 && be == 1.0) ls.wk = WK_SQRT;
+  else if (al == 1.0 && be == -1.0) ls.wk = WK_IS;
+  else ls.wk = WK_GEN;
+  // loss case, in the order of the definition
+  if (al == 1.0 && be == 0.0) ls.lk = LK_KL;
+  else if (al == 1.0 && be == 1.0) ls.lk = LK_EUC;
+  else if (al == 1.0 && be == -1.0) ls.lk = LK_IS;
+  else if (al == 0.5 && be == 1.0) ls.lk = LK_SQRT;
+  else if (be != 0.0 && al + be != 0.0) ls.lk = LK_GENERIC;
+  else if (be == 0.0) ls.lk = LK_BETA0;
+  else ls.lk = LK_AMB;
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pairwise contraction programs
+// ---------------------------------------------------------------------------
+int64_t TensorRef::size_of(const Model& m) const {
+  int64_t n = 1;
+  for (char c : subs) n *= m.size[(unsigned char)c];
+  return n;
+}
+
+std::vector<int64_t> row_major_strides(const Model& m, const std::string& subs, int64_t inner) {
+  std::vector<int64_t> st(subs.size());
+  int64_t s = inner;
+  for (int i = (int)subs.size() - 1; i >= 0; --i) {
+    st[i] = s;
+    s *= m.size[(unsigned char)subs[i]];
+  }
+  return st;
+}
+
+// Contract `in` into `out` (whose subs and strides are fixed), greedily
+// contracting the pair with the smallest intermediate first.  New
+// intermediates are workspace buffers appended to `ws_sizes`.
+std::vector<Step> plan_contraction(const Model& m, std::vector<TensorRef> in, const TensorRef& out,
+                                   std::vector<int64_t>& ws_sizes, int64_t& macs) {
+  std::vector<Step> steps;
+  auto letters_of = [](const std::vector<TensorRef>& v, int skip1, int skip2) {
+    std::set<char> s;
+    for (int i = 0; i < (int)v.size(); ++i)
+      if (i != skip1 && i != skip2)
+        for (char c : v[i].subs) s.insert(c);
+    return s;
+  };
+  while (in.size() > 2) {
+    int bi = -1, bj = -1;
+    int64_t best = -1;
+    std::string best_subs;
+    for (int i = 0; i < (int)in.size(); ++i)
+      for (int j = i + 1; j < (int)in.size(); ++j) {
+        std::set<char> keep = letters_of(in, i, j);
+        for (char c : out.subs) keep.insert(c);
+        std::string subs;
+        std::set<char> u;
+        for (char c : in[i].subs + in[j].subs)
+          if (keep.count(c) && u.insert(c).second) subs.push_back(c);
+        int64_t n = 1;
+        for (char c : subs) n *= m.size[(unsigned char)c];
+        if (best < 0 || n < best) {
+          best = n;
+          bi = i;
+          bj = j;
+          best_subs = subs;
+        }
+      }
+    TensorRef tmp;
+    tmp.kind = TK_WS;
+    tmp.id = (int)ws_sizes.size();
+    tmp.subs = best_subs;
+    tmp.strides = row_major_strides(m, best_subs, 1);
+    ws_sizes.push_back(best);
+    Step st;
+    st.in = {in[bi], in[bj]};
+    st.out = tmp;
+    steps.push_back(st);
+    in.erase(in.begin() + bj);
+    in.erase(in.begin() + bi);
+    in.push_back(tmp);
+  }
+  Step st;
+  st.in = in;
+  st.out = out;
+  steps.push_back(st);
+  for (auto& s : steps) {
+    std::set<char> all;
+    for (auto& t : s.in)
+      for (char c : t.subs) all.insert(c);
+    s.sum.clear();
+    for (char c : all)
+      if (s.out.subs.find(c) == std::string::npos) s.sum.push_back(c);
+    int64_t n = s.out.size_of(m);
+    for (char c : s.sum) n *= m.size[(unsigned char)c];
+    macs += n;
+  }
+  return steps;
+}
+
+// ---------------------------------------------------------------------------
+// Block lowering
+// ---------------------------------------------------------------------------
+static std::string letters_in_order(const std::string& order, const std::set<char>& s) {
+  std::string r;
+  for (char c : order)
+    if (s.count(c)) r.push_back(c);
+  return r;
+}
+
+static int pad_kappa(int64_t K) { return K <= 16 ? 16 : K <= 32 ? 32 : K <= 64 ? 64 : -1; }
+
+Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>& ws_sizes,
+                   std::string& err) {
+  const int L = (int)m.ops.size();
+  const int M = (int)m.out.size();
+  auto obs_of = [&](int o) {
+    std::string r;
+    for (char c : m.ops[o])
+      if (m.out.find(c) != std::string::npos) r.push_back(c);
+    return r;
+  };
+  double best_cost = -1;
+  BlockPlan best;
+  std::vector<int64_t> best_ws;
+  const std::string obs_l = obs_of(ell);
+  for (int pmask = 1; pmask < (1 << M); ++pmask) {
+    std::set<char> P;
+    for (int i = 0; i < M; ++i)
+      if (pmask >> i & 1) P.insert(m.out[i]);
+    bool ok = true;
+    for (char c : obs_l) ok &= P.count(c) > 0;
+    if (!ok) continue;
+    // side of each operand: 0 = P, 1 = Q, -1 = free
+    std::vector<int> side(L, -1);
+    std::vector<int> free_ops;
+    for (int o = 0; o < L && ok; ++o) {
+      std::string ob = obs_of(o);
+      if (ob.empty()) {
+        if (o == ell) side[o] = 0;
+        else free_ops.push_back(o);
+        continue;
+      }
+      int inP = 0;
+      for (char c : ob) inP += P.count(c) ? 1 : 0;
+      if (inP == (int)ob.size()) side[o] = 0;
+      else if (inP == 0) side[o] = 1;
+      else ok = false;
+    }
+    if (!ok) continue;
+    const bool q_empty = (int)P.size() == M;
+    for (int fmask = 0; fmask < (1 << free_ops.size()); ++fmask) {
+      std::vector<int> sd = side;
+      for (size_t f = 0; f < free_ops.size(); ++f) sd[free_ops[f]] = q_empty ? 0 : (fmask >> f & 1);
+      if (q_empty && fmask) break;
+      std::set<char> latP, latQ;
+      for (int o = 0; o < L; ++o)
+        for (char c : m.ops[o])
+          if (m.out.find(c) == std::string::npos) (sd[o] == 0 ? latP : latQ).insert(c);
+      std::set<char> kap;
+      for (char c : latP)
+        if (latQ.count(c)) kap.insert(c);
+      // kappa order: operand l's order if it holds them all, else first appearance
+      std::string kappa = letters_in_order(m.ops[ell], kap);
+      if (kappa.size() != kap.size()) kappa = letters_in_order(m.latent, kap);
+      int64_t K = 1;
+      for (char c : kappa) K *= m.size[(unsigned char)c];
+      const int KP = pad_kappa(K);
+      if (KP < 0) continue;
+
+      BlockPlan bp2;
+      std::vector<int64_t> ws2 = ws_sizes;
+      bp2.ell = ell;
+      bp2.P = letters_in_order(m.out, P);
+      std::set<char> Qs;
+      for (char c : m.out)
+        if (!P.count(c)) Qs.insert(c);
+      bp2.Q = letters_in_order(m.out, Qs);
+      bp2.kappa = kappa;
+      bp2.K = (int)K;
+      bp2.KP = KP;
+      bp2.nP = 1;
+      for (char c : bp2.P) bp2.nP *= m.size[(unsigned char)c];
+      bp2.nQ = 1;
+      for (char c : bp2.Q) bp2.nQ *= m.size[(unsigned char)c];
+      bp2.side = sd;
+      int64_t macs = 0;
+      double mat_elems = 0;
+      // ---- row side L
+      std::vector<TensorRef> pops, qops;
+      for (int o = 0; o < L; ++o) {
+        TensorRef t;
+        t.kind = TK_FACTOR;
+        t.id = o;
+        t.subs = m.ops[o];
+        t.strides = row_major_strides(m, t.subs, 1);
+        (sd[o] == 0 ? pops : qops).push_back(t);
+      }
+      bp2.L_direct = pops.size() == 1 && m.ops[ell] == bp2.P + kappa;
+      if (bp2.L_direct) {
+        bp2.ldL = (int)K;
+      } else {
+        TensorRef out;
+        out.kind = TK_WS;
+        out.id = (int)ws2.size();
+        out.subs = bp2.P + kappa;
+        ws2.push_back(bp2.nP * KP);
+        out.strides = row_major_strides(m, bp2.P, KP);
+        auto ks = row_major_strides(m, kappa, 1);
+        out.strides.insert(out.strides.end(), ks.begin(), ks.end());
+        bp2.L_buf = out.id;
+        bp2.ldL = KP;
+        bp2.L_prog = plan_contraction(m, pops, out, ws2, macs);
+        mat_elems += (double)bp2.nP * KP;
+        // chain-back: N_l = einsum(P-side operands except l, N_L -> ops[l])
+        std::vector<TensorRef> cin;
+        for (auto& t : pops)
+          if (t.id != ell) cin.push_back(t);
+        TensorRef nl;
+        nl.kind = TK_NL;
+        nl.id = 0;
+        nl.subs = bp2.P + kappa;
+        nl.strides = row_major_strides(m, nl.subs, 1);
+        cin.push_back(nl);
+        TensorRef no;
+        no.kind = TK_WS;
+        no.id = (int)ws2.size();
+        no.subs = m.ops[ell];
+        no.strides = row_major_strides(m, no.subs, 1);
+        ws2.push_back(no.size_of(m));
+        bp2.Nl_buf = no.id;
+        int64_t cb = 0;
+        bp2.chainN = plan_contraction(m, cin, no, ws2, cb);
+        for (auto& t : cin)
+          if (t.kind == TK_NL) t.kind = TK_DL;
+        no.id = (int)ws2.size();
+        ws2.push_back(no.size_of(m));
+        bp2.Dl_buf = no.id;
+        bp2.chainD = plan_contraction(m, cin, no, ws2, cb);
+        macs += cb;
+        bp2.NL_buf = (int)ws2.size();
+        ws2.push_back(bp2.nP * K);
+        bp2.DL_buf = (int)ws2.size();
+        ws2.push_back(bp2.nP * K);
+      }
+      // ---- column side R: product of pieces, or one materialised piece
+      bool kr = !q_empty && !qops.empty() && (int)qops.size() <= kMaxPieces;
+      for (auto& t : qops) {
+        std::string ob;
+        for (char c : t.subs)
+          if (m.out.find(c) != std::string::npos) ob.push_back(c);
+        kr &= !ob.empty() && t.subs == ob + kappa;
+      }
+      bp2.pieces.clear();
+      if (kr) {
+        for (auto& t : qops) {
+          Piece pc;
+          pc.factor = t.id;
+          pc.ld = (int)K;
+          pc.obs.clear();
+          for (char c : t.subs)
+            if (m.out.find(c) != std::string::npos) pc.obs.push_back(c);
+          pc.nrows = 1;
+          for (char c : pc.obs) pc.nrows *= m.size[(unsigned char)c];
+          bp2.pieces.push_back(pc);
+        }
+      } else {
+        Piece pc;
+        pc.factor = -1;
+        pc.ld = KP;
+        pc.nrows = bp2.nQ;
+        if (q_empty) {
+          pc.ws = (int)ws2.size();  // a single row [1, 0, ...]
+          ws2.push_back(KP);
+          bp2.ones_buf = pc.ws;
+        } else {
+          TensorRef out;
+          out.kind = TK_WS;
+          out.id = (int)ws2.size();
+          out.subs = bp2.Q + kappa;
+          ws2.push_back(bp2.nQ * KP);
+          out.strides = row_major_strides(m, bp2.Q, KP);
+          auto ks = row_major_strides(m, kappa, 1);
+          out.strides.insert(out.strides.end(), ks.begin(), ks.end());
+          pc.ws = out.id;
+          bp2.R_prog = plan_contraction(m, qops, out, ws2, macs);
+          mat_elems += (double)bp2.nQ * KP;
+        }
+        bp2.pieces.push_back(pc);
+      }
+      // ---- cost: fused MFMA work on padded tiles, plus the generic contractions
+      const int rows = KP == 64 ? 32 : 64;
+      const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nQ;
+      const double cost = Neff * 6.0 * KP + 16.0 * macs + 8.0 * mat_elems;
+      if (best_cost < 0 || cost < best_cost) {
+        best_cost = cost;
+        best = bp2;
+        best_ws = ws2;
+      }
+    }
+  }
+  if (best_cost < 0) {
+    err = "block " + std::to_string(ell) + " ('" + m.ops[ell] +
+          "') has no lowering with a contraction width <= 64";
+    return ST_UNSUPPORTED;
+  }
+  bp = best;
+  ws_sizes = best_ws;
+  return ST_OK;
+}
+
+// Element offsets in Y (row-major over the output letters) of every
+// multi-index over `letters` (enumerated row-major, last letter fastest).
+std::vector<uint32_t> offsets_table(const Model& m, const std::string& letters) {
+  std::vector<int64_t> ystride(m.out.size());
+  int64_t s = 1;
+  for (int i = (int)m.out.size() - 1; i >= 0; --i) {
+    ystride[i] = s;
+    s *= m.size[(unsigned char)m.out[i]];
+  }
+  std::vector<int64_t> sz, st;
+  for (char c : letters) {
+    sz.push_back(m.size[(unsigned char)c]);
+    st.push_back(ystride[m.out.find(c)]);
+  }
+  int64_t n = 1;
+  for (auto v : sz) n *= v;
+  std::vector<uint32_t> t((size_t)n);
+  std::vector<int64_t> idx(sz.size(), 0);
+  int64_t off = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    t[(size_t)i] = (uint32_t)off;
+    for (int d = (int)sz.size() - 1; d >= 0; --d) {
+      ++idx[d];
+      off += st[d];
+      if (idx[d] < sz[d]) break;
+      off -= sz[d] * st[d];
+      idx[d] = 0;
+    }
+  }
+  return t;
+}
+
+// Row of every column multi-index q (over Q letters) in a piece whose
+// observed letters are `obs` (in the piece's own order).
+std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, const std::string& obs) {
+  std::vector<int64_t> rstride(obs.size());
+  int64_t s = 1;
+  for (int i = (int)obs.size() - 1; i >= 0; --i) {
+    rstride[i] = s;
+    s *= m.size[(unsigned char)obs[i]];
+  }
+  std::vector<int64_t> sz, st;
+  for (char c : Q) {
+    sz.push_back(m.size[(unsigned char)c]);
+    const size_t pos = obs.find(c);
+    st.push_back(pos == std::string::npos ? 0 : rstride[pos]);
+  }
+  int64_t n = 1;
+  for (auto v : sz) n *= v;
+  std::vector<uint32_t> t((size_t)n);
+  std::vector<int64_t> idx(sz.size(), 0);
+  int64_t off = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    t[(size_t)i] = (uint32_t)off;
+    for (int d = (int)sz.size() - 1; d >= 0; --d) {
+      ++idx[d];
+      off += st[d];
+      if (idx[d] < sz[d]) break;
+      off -= sz[d] * st[d];
+      idx[d] = 0;
+    }
+  }
+  return t;
+}
+
+bool piece_is_identity(const Model& m, const std::string& Q, const std::string& obs) {
+  (void)m;
+  return obs == Q;
+}
+
+bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg) {
+  const int rows = bp.KP == 64 ? 32 : 64;
+  bp.n_panels = (int)((bp.nP + rows - 1) / rows);
+  const int64_t qsteps = (bp.nQ + 15) / 16;
+  int64_t chunks = std::max<int64_t>(1, (target_wg + bp.n_panels - 1) / bp.n_panels);
+  chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (qsteps + 3) / 4));
+  const int64_t steps_per_wave = (qsteps + 4 * chunks - 1) / (4 * chunks);
+  bp.q_per_wave = (int)(16 * steps_per_wave);
+  bp.n_chunks = (int)((bp.nQ + 4 * (int64_t)bp.q_per_wave - 1) / (4 * (int64_t)bp.q_per_wave));
+  const int64_t nwg = (int64_t)bp.n_panels * bp.n_chunks;
+  if (nwg >= (int64_t(1) << 31)) return false;
+  bp.n_wg = (int)nwg;
+  bp.xcd_remap = (bp.n_wg % 8 == 0 && bp.n_wg >= 64) ? 1 : 0;
+  const char last = m.out.back();
+  bp.vecq = bp.Q.find(last) != std::string::npos && m.size[(unsigned char)last] % 4 == 0;
+  return true;
+}
+
+std::string describe_block(const Model& m, const BlockPlan& bp) {
+  std::ostringstream o;
+  o << "block " << bp.ell << " '" << m.ops[bp.ell] << "': P={" << bp.P << "} Q={" << bp.Q
+    << "} kappa={" << bp.kappa << "} K=" << bp.K << " KP=" << bp.KP << " nP=" << bp.nP
+    << " nQ=" << bp.nQ << " L=" << (bp.L_direct ? "direct" : "materialised") << " R=";
+  if (bp.pieces.size() == 1 && bp.pieces[0].factor < 0) o << "materialised";
+  else {
+    o << "product(";
+    for (size_t i = 0; i < bp.pieces.size(); ++i)
+      o << (i ? "," : "") << m.ops[bp.pieces[i].factor];
+    o << ")";
+  }
+  o << (bp.L_direct ? "" : " chain-back") << (bp.vecq ? " vecq" : "") << " grid=" << bp.n_wg
+    << " chunks=" << bp.n_chunks << " q/wave=" << bp.q_per_wave;
+  return o.str();
+}
+
+}  // namespace nnef

@@ -1,0 +1,84 @@
+// Host-side plan structures of libnnef.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nnef_internal.hpp"
+
+namespace nnef {
+
+enum Status { ST_OK = 0, ST_PARSE = 1, ST_SHAPE = 2, ST_LOSS = 3, ST_ARG = 4, ST_DEVICE = 5,
+              ST_NOMEM = 6, ST_UNSUPPORTED = 7 };
+
+struct Model {
+  std::vector<std::string> ops;  // operand subscripts
+  std::string out;               // observed letters, in Y's axis order
+  std::string latent;            // contracted letters, first-appearance order
+  int64_t size[128] = {0};       // size of every letter
+};
+
+// Operand of a contraction program.
+enum TensorKind { TK_FACTOR = 0, TK_WS = 1, TK_NL = 2, TK_DL = 3 };
+struct TensorRef {
+  int kind = TK_FACTOR;
+  int id = 0;                      // factor index or workspace buffer index
+  std::string subs;
+  std::vector<int64_t> strides;    // element stride of every letter of subs
+  int64_t size_of(const Model& m) const;
+};
+struct Step {
+  std::vector<TensorRef> in;
+  TensorRef out;
+  std::string sum;                 // letters summed over
+};
+
+// One factor of the column-side product, or one materialised buffer.
+struct Piece {
+  int factor = -1;                 // factor index, or -1 for workspace buffer `ws`
+  int ws = -1;
+  int ld = 0;                      // row stride (elements)
+  int64_t nrows = 0;
+  std::string obs;                 // observed letters, in the factor's order
+  int idx_buf = -1;                // device table slot of the row index (or -1: identity)
+};
+
+struct BlockPlan {
+  int ell = 0;
+  std::string P, Q, kappa;
+  int K = 1, KP = 16;
+  int64_t nP = 1, nQ = 1;
+  std::vector<int> side;           // 0 = row side, 1 = column side, per operand
+  bool L_direct = false;
+  int ldL = 0;
+  int L_buf = -1;                  // workspace buffer of a materialised L
+  std::vector<Step> L_prog;        // builds L (row side) from the current factors
+  std::vector<Step> R_prog;        // builds a materialised R
+  std::vector<Piece> pieces;
+  int ones_buf = -1;               // R = [1] when every mode is on the row side
+  std::vector<Step> chainN, chainD;
+  int NL_buf = -1, DL_buf = -1;    // [nP][K] reduced N_L, D_L
+  int Nl_buf = -1, Dl_buf = -1;    // N_l, D_l shaped like operand l
+  // launch geometry and device tables (filled by the ABI layer)
+  bool vecq = false;
+  int n_panels = 0, q_per_wave = 0, n_chunks = 0, n_wg = 0;
+  int xcd_remap = 0;
+  uint32_t* d_poff = nullptr;
+  uint32_t* d_qoff = nullptr;
+  uint32_t* d_pidx[kMaxPieces] = {nullptr, nullptr, nullptr};
+};
+
+Status parse_model(const std::string& s, Model& m, std::string& err);
+Status make_loss(double alpha, double beta, LossSpec& ls, std::string& err);
+Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>& ws_sizes,
+                   std::string& err);
+std::vector<Step> plan_contraction(const Model& m, std::vector<TensorRef> in, const TensorRef& out,
+                                   std::vector<int64_t>& ws_sizes, int64_t& macs);
+std::vector<int64_t> row_major_strides(const Model& m, const std::string& subs, int64_t inner);
+std::vector<uint32_t> offsets_table(const Model& m, const std::string& letters);
+std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, const std::string& obs);
+bool piece_is_identity(const Model& m, const std::string& Q, const std::string& obs);
+bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg);
+std::string describe_block(const Model& m, const BlockPlan& bp);
+
+}  // namespace nnef

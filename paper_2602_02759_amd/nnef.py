@@ -1,0 +1,219 @@
+"""Python binding of libnnef (C ABI in ``include/nnef.h``).
+
+Argument marshalling only: every step of a sweep runs in the library's HIP
+kernels.  The functions keep the C names (``nnef_plan``, ``nnef_step``,
+``nnef_loss``, ...); ``Plan`` is a small owner object around them.  Tensors are
+torch tensors on the GPU: Y float32, mask uint8 (1 = observed) or None, factors
+float32, all contiguous, in the layouts the header documents.
+
+There is no fallback: if ``libnnef.so`` is missing or fails to load, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnnef.so")
+_lib = None
+
+STATUS = {0: "NNEF_OK", 1: "NNEF_E_PARSE", 2: "NNEF_E_SHAPE", 3: "NNEF_E_LOSS_UNSUPPORTED",
+          4: "NNEF_E_ARG", 5: "NNEF_E_DEVICE", 6: "NNEF_E_NOMEM", 7: "NNEF_E_UNSUPPORTED"}
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+
+class NnefError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("prec", ctypes.c_int), ("deterministic", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
+
+
+EXPORTS = {
+    "nnef_default_options": (None, [ctypes.POINTER(Options)]),
+    "nnef_plan": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, ctypes.POINTER(Options),
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "nnef_plan_destroy": (None, [ctypes.c_void_p]),
+    "nnef_plan_num_factors": (ctypes.c_int, [ctypes.c_void_p]),
+    "nnef_plan_factor_numel": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int]),
+    "nnef_plan_describe": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
+    "nnef_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.c_void_p]),
+    "nnef_loss": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.c_void_p]),
+    "nnef_loss_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "nnef_plan_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "nnef_plan_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "nnef_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libnnef.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        # torch bundles its own libamdhip64.so.7; load it first so that the
+        # library binds to the same HIP runtime instead of a second copy.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise NnefError(st, lib().nnef_last_error().decode())
+
+
+def _ptr(t, dtype, what):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _factor_array(factors, numels=None):
+    import torch
+    arr = (ctypes.c_void_p * len(factors))()
+    for i, f in enumerate(factors):
+        arr[i] = _ptr(f, torch.float32, f"factor {i}")
+        if numels is not None and f.numel() != numels[i]:
+            raise ValueError(f"factor {i} has {f.numel()} elements, the plan expects {numels[i]}")
+    return arr
+
+
+# ------------------------------------------------------------------ C-named calls
+def nnef_plan(model_str, mode_sizes, ranks, alpha, beta, eps=1e-10, prec="fp32"):
+    opt = Options()
+    lib().nnef_default_options(ctypes.byref(opt))
+    opt.eps = eps
+    opt.prec = PREC[prec]
+    ms = (ctypes.c_int64 * len(mode_sizes))(*mode_sizes)
+    rk = (ctypes.c_int64 * max(1, len(ranks)))(*ranks)
+    h = ctypes.c_void_p()
+    _check(lib().nnef_plan(model_str.encode(), ms, len(mode_sizes), rk, len(ranks),
+                           float(alpha), float(beta), ctypes.byref(opt), ctypes.byref(h)))
+    return h
+
+
+def nnef_plan_destroy(h):
+    lib().nnef_plan_destroy(h)
+
+
+def nnef_plan_describe(h):
+    n = lib().nnef_plan_describe(h, None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().nnef_plan_describe(h, buf, n + 1)
+    return buf.value.decode()
+
+
+def nnef_plan_set_timing(h, enable):
+    _check(lib().nnef_plan_set_timing(h, int(bool(enable))))
+
+
+def nnef_plan_timing(h):
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(lib().nnef_plan_timing(h, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def nnef_step(h, Y, M, factors, n_sweeps, loss_trace=None, stream=None):
+    import torch
+    _check(lib().nnef_step(h, _ptr(Y, torch.float32, "Y"), _ptr(M, torch.uint8, "mask"),
+                           _factor_array(factors), int(n_sweeps),
+                           _ptr(loss_trace, torch.float64, "loss_trace"), _stream(stream)))
+
+
+def nnef_loss(h, Y, M, factors, stream=None):
+    import torch
+    out = ctypes.c_double()
+    _check(lib().nnef_loss(h, _ptr(Y, torch.float32, "Y"), _ptr(M, torch.uint8, "mask"),
+                           _factor_array(factors), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def nnef_loss_device(h, Y, M, factors, d_out, stream=None):
+    import torch
+    _check(lib().nnef_loss_device(h, _ptr(Y, torch.float32, "Y"), _ptr(M, torch.uint8, "mask"),
+                                  _factor_array(factors), _ptr(d_out, torch.float64, "d_out"),
+                                  _stream(stream)))
+
+
+class Plan:
+    """Owner of an ``nnef_plan_t``; the methods call the C entry points."""
+
+    def __init__(self, model_str, mode_sizes, ranks, alpha, beta, eps=1e-10, prec="fp32"):
+        self.model_str = model_str
+        self.h = nnef_plan(model_str, list(mode_sizes), list(ranks), alpha, beta, eps, prec)
+        n = lib().nnef_plan_num_factors(self.h)
+        self.numels = [lib().nnef_plan_factor_numel(self.h, i) for i in range(n)]
+
+    def describe(self):
+        return nnef_plan_describe(self.h)
+
+    def _check_factors(self, factors):
+        if len(factors) != len(self.numels):
+            raise ValueError(f"expected {len(self.numels)} factors, got {len(factors)}")
+        _factor_array(factors, self.numels)
+
+    def step(self, Y, M, factors, n_sweeps=1, loss_trace=None, stream=None):
+        self._check_factors(factors)
+        nnef_step(self.h, Y, M, factors, n_sweeps, loss_trace, stream)
+
+    def loss(self, Y, M, factors, stream=None):
+        self._check_factors(factors)
+        return nnef_loss(self.h, Y, M, factors, stream)
+
+    def loss_device(self, Y, M, factors, d_out, stream=None):
+        self._check_factors(factors)
+        nnef_loss_device(self.h, Y, M, factors, d_out, stream)
+
+    def set_timing(self, enable=True):
+        nnef_plan_set_timing(self.h, enable)
+
+    def timing(self):
+        """(number of fused passes timed, their total milliseconds)."""
+        return nnef_plan_timing(self.h)
+
+    def close(self):
+        if self.h:
+            nnef_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

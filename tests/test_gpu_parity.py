@@ -1,0 +1,183 @@
+"""GPU <-> FP64 oracle parity of the plain FP32 path, through the C ABI.
+
+Tolerances: one sweep from an identical state matches the oracle at relative
+1e-5 per factor (Frobenius, plus an elementwise bound); losses at 1e-5; a full
+trajectory's final loss at 1e-4 relative, both losses evaluated by the oracle.
+Sizes are chosen so the oracle runs in seconds while the kernels still see
+several tiles and ragged tails; the CP 256^3 R=32 case is the full benchmark
+size.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2602_02759_amd import datagen
+
+from _gpu_util import (EPS, assert_step_parity, clamp_init, gpu_sweeps, oracle_sweep, to_dev)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _plan(p):
+    from paper_2602_02759_amd.nnef import Plan
+    return Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, eps=EPS)
+
+
+def _case(name):
+    if name == "nmf":
+        return datagen.nmf_kl()
+    if name == "cp3_small_euc":
+        return datagen.cp3(1.0, 1.0, sizes=dict(i=48, j=40, k=36), R=32, seed=21)
+    if name == "cp3_small_ab":
+        return datagen.cp3(0.5, 1.0, sizes=dict(i=48, j=40, k=36), R=32, seed=22)
+    if name == "cp3_ragged_kl":
+        return datagen.cp3(1.0, 0.0, sizes=dict(i=37, j=29, k=23), R=5, seed=23)
+    if name == "cp3_ragged_gen":
+        return datagen.cp3(0.7, 0.3, sizes=dict(i=37, j=29, k=23), R=5, seed=24)
+    if name == "cp3_full_euc":
+        return datagen.cp3(1.0, 1.0)
+    if name == "cp3_full_ab":
+        return datagen.cp3(0.5, 1.0)
+    if name == "tucker_small":
+        return datagen.tucker3(I=30, J=26, K=18, Ra=6, Rb=5, Rc=4, seed=31)
+    if name == "tucker_mid":
+        return datagen.tucker3(I=96, J=80, K=40, Ra=32, Rb=32, Rc=16, seed=32)
+    if name == "tt_small":
+        return datagen.tt4(I=13, J=11, K=9, Lm=7, Ra=3, Rb=4, Rc=5, seed=41)
+    if name == "tt_mid":
+        return datagen.tt4(I=40, J=36, K=28, Lm=20, Ra=16, Rb=16, Rc=16, seed=42)
+    if name == "cp4_r64":
+        return datagen.poisson_problem("cp4", "ir,jr,kr,lr->ijkl",
+                                       dict(i=17, j=40, k=23, l=12, r=64), 1.0, 0.0, seed=51,
+                                       truth_shape=0.5)
+    if name == "cp4_r4":
+        return datagen.poisson_problem("cp4", "ir,jr,kr,lr->ijkl",
+                                       dict(i=33, j=41, k=35, l=32, r=4), 1.0, 0.0, seed=52,
+                                       truth_shape=0.5)
+    if name == "manybody":
+        return datagen.poisson_problem("mb", "ij,jk,ik->ijk", dict(i=19, j=17, k=13), 1.0, 0.0,
+                                       seed=61, truth_shape=1.0, missing=0.1)
+    if name == "uber":
+        return datagen.poisson_problem("uber", "wr,dr,hr,irk,jrk->wdhij",
+                                       dict(w=5, d=7, h=6, i=10, j=9, r=4, k=3), 1.0, 0.0, seed=62,
+                                       truth_shape=0.5, missing=0.1)
+    if name == "icews":
+        return datagen.poisson_problem("icews", "ir,jr,ak,kr,tr->ijat",
+                                       dict(i=12, j=12, a=5, t=9, r=6, k=2), 1.3, 1.0, seed=63,
+                                       truth_shape=0.5, missing=0.1)
+    if name == "rkl":
+        return datagen.gamma_noise_problem("rkl", "ir,jr,kr->ijk", dict(i=20, j=24, k=18, r=6),
+                                           0.0, 1.0, seed=64, missing=0.2)
+    if name == "hellinger":
+        return datagen.gamma_noise_problem("hel", "ir,jr,kr->ijk", dict(i=20, j=24, k=18, r=6),
+                                           0.5, 0.5, seed=65, missing=0.2)
+    if name == "is":
+        return datagen.gamma_noise_problem("is", "ir,jr,kr->ijk", dict(i=20, j=24, k=18, r=6),
+                                           1.0, -1.0, seed=66, missing=0.2)
+    raise KeyError(name)
+
+
+SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_gen", "tucker_small",
+         "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
+         "hellinger", "is"]
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_one_sweep_matches_oracle(name):
+    p = _case(name)
+    print(f"[parity] {name} {p.model_str} sizes={p.sizes} ab=({p.alpha},{p.beta})", flush=True)
+    plan = _plan(p)
+    print(plan.describe(), flush=True)
+    s0 = clamp_init(p)
+    g1 = gpu_sweeps(plan, p, s0, 1)
+    r1 = oracle_sweep(p, s0)
+    assert_step_parity(g1, r1, TOL, name)
+    # a second step from the GPU's own state (promoted to FP64)
+    g2 = gpu_sweeps(plan, p, g1, 1)
+    r2 = oracle_sweep(p, g1)
+    assert_step_parity(g2, r2, TOL, name + " step 2")
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_loss_matches_oracle(name):
+    p = _case(name)
+    plan = _plan(p)
+    s0 = clamp_init(p)
+    Y = to_dev(p.Y)
+    M = to_dev(p.M) if p.M is not None else None
+    f = [to_dev(s) for s in s0]
+    got = plan.loss(Y, M, f)
+    ref = O.loss(p.model_str, [s.astype(np.float64) for s in s0], p.Y, p.M, p.alpha, p.beta)
+    assert abs(got - ref) <= 1e-5 * abs(ref), (got, ref)
+
+
+@pytest.mark.parametrize("name", ["cp3_full_euc", "cp3_full_ab"])
+def test_full_size_cp3_step(name):
+    """The benchmark workload: CP 256^3, R = 32, 20 % missing, one sweep."""
+    p = _case(name)
+    print(f"[parity] {name}", flush=True)
+    plan = _plan(p)
+    s0 = clamp_init(p)
+    g1 = gpu_sweeps(plan, p, s0, 1)
+    assert_step_parity(g1, oracle_sweep(p, s0), TOL, name)
+
+
+def test_nmf_trajectory_final_loss():
+    """Config 1 (NMF KL 200x150 R=8): 100 sweeps; per-step parity at t in
+    {0, 1, 10, 99} and final loss within 1e-4 of the oracle's own run."""
+    p = _case("nmf")
+    plan = _plan(p)
+    s = clamp_init(p)
+    for t in range(100):
+        g = gpu_sweeps(plan, p, s, 1)
+        if t in (0, 1, 10, 99):
+            assert_step_parity(g, oracle_sweep(p, s), TOL, f"nmf t={t}")
+        s = g
+    ref = O.fit(p.model_str, p.init, p.Y, None, p.alpha, p.beta, EPS, n_sweeps=100)
+    lg = O.loss(p.model_str, [x.astype(np.float64) for x in s], p.Y, None, p.alpha, p.beta)
+    lr = O.loss(p.model_str, ref, p.Y, None, p.alpha, p.beta)
+    assert abs(lg - lr) <= 1e-4 * lr, (lg, lr)
+
+
+def test_loss_trace_monotone_and_matches():
+    p = _case("cp3_small_ab")
+    plan = _plan(p)
+    s0 = clamp_init(p)
+    g, tr = gpu_sweeps(plan, p, s0, 20, trace=True)
+    assert np.all(np.diff(tr) <= 1e-6 * tr[:-1]), tr
+    ref = O.loss(p.model_str, [s.astype(np.float64) for s in s0], p.Y, p.M, p.alpha, p.beta)
+    assert abs(tr[0] - ref) <= 1e-5 * ref
+
+
+def test_masked_values_never_read():
+    import torch
+    p = _case("cp3_small_euc")
+    plan = _plan(p)
+    s0 = clamp_init(p)
+    Yn = p.Y.copy()
+    Yn[p.M == 0] = np.nan
+    a = gpu_sweeps(plan, p, s0, 2)
+    b = gpu_sweeps(plan, p, s0, 2, Y=to_dev(Yn))
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    pk = _case("cp3_ragged_kl")
+    plk = _plan(pk)
+    s1 = clamp_init(pk)
+    c = gpu_sweeps(plk, pk, s1, 1, M=torch.ones(pk.Y.shape, dtype=torch.uint8, device="cuda:0"))
+    d = gpu_sweeps(plk, pk, s1, 1, M="none")   # KL without a mask: D in closed form
+    for x, y in zip(c, d):
+        np.testing.assert_allclose(x, y, rtol=2e-6)
+
+
+def test_deterministic_and_resumable():
+    p = _case("cp3_small_ab")
+    plan = _plan(p)
+    s0 = clamp_init(p)
+    a = gpu_sweeps(plan, p, s0, 3)
+    b = gpu_sweeps(plan, p, s0, 3)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    c = gpu_sweeps(plan, p, gpu_sweeps(plan, p, s0, 1), 2)
+    for x, y in zip(a, c):
+        np.testing.assert_array_equal(x, y)
