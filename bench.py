@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--cpu-sweeps", type=int, default=3,
                     help="oracle sweeps timed for the CPU baseline (0 disables)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of Y (a reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -89,6 +91,11 @@ def main():
     plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta)
     stream = torch.cuda.current_stream()
 
+    if args.copy_calibration:
+        Yc = torch.empty_like(Y)
+        Yc.copy_(Y)
+        torch.cuda.synchronize()
+        del Yc
     plan.step(Y, M, f, n_sweeps=args.warmup)
     torch.cuda.synchronize()
     plan.set_timing(True)

@@ -87,7 +87,7 @@ void nnef_default_options(nnef_options* opt);
  *                 a letter repeated inside one operand or in the output, an
  *                 output letter used by no operand;
  *   NNEF_E_SHAPE  n_modes / n_ranks not matching the string, a size <= 0,
- *                 2^31 or more data entries;
+ *                 2^30 or more data entries;
  *   NNEF_E_LOSS_UNSUPPORTED  alpha = 0 with beta != 1 (App. B gives no
  *                 decomposition), non-finite alpha or beta;
  *   NNEF_E_UNSUPPORTED  a block whose contraction width exceeds 64 in every

@@ -154,9 +154,9 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
     }
     m.size[(unsigned char)m.out[i]] = mode_sizes[i];
     N *= mode_sizes[i];
-    if (N >= (int64_t(1) << 31)) {
+    if (N >= (int64_t(1) << 30)) {
       free_plan(p);
-      return fail(NNEF_E_SHAPE, "the data tensor must have fewer than 2^31 entries");
+      return fail(NNEF_E_SHAPE, "the data tensor must have fewer than 2^30 entries");
     }
   }
   for (int i = 0; i < n_ranks; ++i) {
@@ -193,6 +193,21 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
     p->max_wg = std::max(p->max_wg, bp.n_wg);
     p->blocks.push_back(bp);
   }
+  // ---- every buffer the kernels index with 32-bit offsets stays below 2^30 elements
+  for (auto v : p->numel)
+    if (v >= (int64_t(1) << 30)) {
+      free_plan(p);
+      return fail(NNEF_E_SHAPE, "a factor has 2^30 or more elements");
+    }
+  for (auto v : p->ws_sizes)
+    if (v >= (int64_t(1) << 30)) {
+      free_plan(p);
+      return fail(NNEF_E_SHAPE, "an intermediate of the lowering has 2^30 or more elements");
+    }
+  if (part_elems >= (size_t(1) << 30)) {
+    free_plan(p);
+    return fail(NNEF_E_SHAPE, "partial sums need 2^30 or more elements");
+  }
   // ---- device memory
   size_t ws_total = 0;
   for (auto s : p->ws_sizes) ws_total += (size_t)((s + 63) / 64 * 64);
@@ -221,12 +236,13 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
   }
   for (auto& bp : p->blocks) {
     nnef_status st = upload_table(p, offsets_table(m, bp.P), &bp.d_poff);
-    if (st == NNEF_OK) st = upload_table(p, offsets_table(m, bp.Q), &bp.d_qoff);
-    for (size_t i = 0; st == NNEF_OK && i < bp.pieces.size(); ++i) {
-      Piece& pc = bp.pieces[i];
-      if (pc.factor >= 0 && !piece_is_identity(m, bp.Q, pc.obs))
-        st = upload_table(p, piece_rows_table(m, bp.Q, pc.obs), &bp.d_pidx[i]);
+    if (st == NNEF_OK) st = upload_table(p, offsets_table(m, bp.qo), &bp.d_qoyoff);
+    if (st == NNEF_OK) {
+      auto ib = inner_base_table(m, bp);
+      if (!all_zero(ib)) st = upload_table(p, ib, &bp.d_inbase);
     }
+    for (size_t i = 0; st == NNEF_OK && i < bp.outers.size(); ++i)
+      st = upload_table(p, outer_row_table(m, bp, bp.outers[i]), &bp.d_orow[i]);
     if (st == NNEF_OK && bp.ones_buf >= 0) {
       const float one = 1.0f;
       if (hipMemcpy(p->ws[bp.ones_buf], &one, sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
@@ -293,6 +309,10 @@ static int run_program(const nnef_plan_s* p, const BlockPlan& bp, const std::vec
   return 0;
 }
 
+static const float* piece_ptr(const nnef_plan_s* p, const Piece& pc, const float* const* factors) {
+  return pc.factor >= 0 ? factors[pc.factor] : p->ws[pc.ws];
+}
+
 static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const float* Y,
                             const uint8_t* M, const float* const* factors) {
   FusedArgs a;
@@ -300,33 +320,44 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.Y = Y;
   a.M = M;
   a.p_off = bp.d_poff;
-  a.q_off = bp.d_qoff;
   a.L = bp.L_direct ? factors[bp.ell] : p->ws[bp.L_buf];
   a.ldL = bp.ldL;
   a.K = bp.K;
   a.nP = (int)bp.nP;
-  a.nQ = (int)bp.nQ;
-  a.npieces = (int)bp.pieces.size();
-  for (int i = 0; i < a.npieces; ++i) {
-    const Piece& pc = bp.pieces[i];
-    a.piece[i] = pc.factor >= 0 ? factors[pc.factor] : p->ws[pc.ws];
-    a.pidx[i] = bp.d_pidx[i];
-    a.ldpiece[i] = pc.ld;
+  a.nqo = (int)bp.nqo;
+  a.nqi = (int)bp.nqi;
+  a.nqis = (int)((bp.nqi + 15) / 16);
+  a.qi_ystride = (int)bp.qi_ystride;
+  a.qo_yoff = bp.d_qoyoff;
+  const Piece& in = bp.pieces[bp.inner];
+  a.inner = piece_ptr(p, in, factors);
+  a.ld_in = in.ld;
+  a.in_stride = (int)bp.in_stride;
+  a.in_base = bp.d_inbase;
+  a.nouter = (int)bp.outers.size();
+  for (int i = 0; i < a.nouter; ++i) {
+    const Piece& pc = bp.pieces[bp.outers[i]];
+    a.outer[i] = piece_ptr(p, pc, factors);
+    a.ld_out[i] = pc.ld;
+    a.orow[i] = bp.d_orow[i];
   }
+  a.n_steps = bp.n_steps;
   a.n_panels = bp.n_panels;
-  a.q_per_wave = bp.q_per_wave;
+  a.steps_per_wave = bp.steps_per_wave;
   a.n_chunks = bp.n_chunks;
   a.n_wg = bp.n_wg;
   a.xcd_remap = bp.xcd_remap;
   a.partN = p->partN;
   a.partD = p->partD;
-  a.no_d = (p->ls.b_is_one() && M == nullptr) ? 1 : 0;
+  a.no_d = (p->ls.b_is_one() && M == nullptr && bp.pieces_disjoint) ? 1 : 0;
   a.alpha = (float)p->ls.alpha;
   a.beta = (float)p->ls.beta;
   const double ab = p->ls.alpha * p->ls.beta, apb = p->ls.alpha + p->ls.beta;
   a.ab_inv = ab != 0 ? (float)(1.0 / ab) : 0.f;
   a.apb_inv = apb != 0 ? (float)(1.0 / apb) : 0.f;
   a.lk = p->ls.lk;
+  const int rows = bp.KP == 16 ? 64 : bp.KP == 32 ? 16 * kPT32 : 16;
+  a.full = (bp.K == bp.KP && bp.nqi % 16 == 0 && bp.nP % rows == 0) ? 1 : 0;
   return a;
 }
 
@@ -360,7 +391,7 @@ nnef_status nnef_step(nnef_plan_t p, const float* Y, const uint8_t* M, float* co
             hipEventRecord(ev0, s) != hipSuccess)
           return fail(NNEF_E_DEVICE, "timing event set-up failed");
       }
-      e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, s);
+      e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, want_loss ? 1 : 0, s);
       if (e) return hip_fail(e, "fused pass launch");
       if (p->timing) {
         if (hipEventRecord(ev1, s) != hipSuccess) return fail(NNEF_E_DEVICE, "timing event record failed");
@@ -375,10 +406,10 @@ nnef_status nnef_step(nnef_plan_t p, const float* Y, const uint8_t* M, float* co
       ua.K = bp.K;
       ua.KP = bp.KP;
       ua.no_d = fa.no_d;
-      ua.npieces = fa.npieces;
-      for (int i = 0; i < fa.npieces; ++i) {
-        ua.piece[i] = fa.piece[i];
-        ua.ldpiece[i] = fa.ldpiece[i];
+      ua.npieces = (int)bp.pieces.size();
+      for (int i = 0; i < ua.npieces; ++i) {
+        ua.piece[i] = piece_ptr(p, bp.pieces[i], cf);
+        ua.ldpiece[i] = bp.pieces[i].ld;
         ua.nrows[i] = bp.pieces[i].nrows;
       }
       ua.theta = bp.L_direct ? factors[l] : nullptr;
@@ -448,9 +479,8 @@ nnef_status nnef_loss_device(nnef_plan_t p, const float* Y, const uint8_t* M,
   int e = run_side_prep(p, bp, factors, s);
   if (e) return hip_fail(e, "side-operand contraction launch");
   FusedArgs fa = fused_args(p, bp, Y, M, factors);
-  fa.loss_only = 1;
   fa.loss_part = p->loss_part;
-  e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, s);
+  e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, 2, s);
   if (e) return hip_fail(e, "loss pass launch");
   e = launch_loss_final(p->loss_part, bp.n_wg, d_loss, s);
   if (e) return hip_fail(e, "loss reduction launch");

@@ -40,37 +40,49 @@ struct LossSpec {
 // Kernel argument blocks (plain data, passed by value).
 // ---------------------------------------------------------------------------
 // Fused pass: for a split of the observed modes into P (rows) and Q (columns),
-//   yhat[p,q] = sum_k L[p,k] R[q,k]          (R[q,k] = prod_m piece_m[idx_m[q],k])
+//   yhat[p,q] = sum_k L[p,k] R[q,k]
 //   Wa = m * a(y, yhat), Wb = m * b(y, yhat)
 //   N[p,k] = sum_q Wa[p,q] R[q,k],  D[p,k] = sum_q Wb[p,q] R[q,k]
-// One workgroup = 4 waves on one panel of rows and 4 consecutive q ranges; it
-// writes one partial N, D of shape [nP][KP] at slot (q chunk).
+// A column q is a pair (qo, qi): qi runs over the last column-side mode and qo
+// over the others, q = qo * nqi + qi.  One step covers 16 consecutive qi at one
+// qo, so every per-qo quantity is uniform across a wave.  The column side is
+//   R[q,k] = inner[(in_base[qo] + qi * in_stride) * ld_in + k]
+//            * prod_m outer_m[orow_m[qo] * ld_out_m + k],
+// either a product of factors (CP-like models) or one materialised buffer.
+// One workgroup = 4 waves on one panel of rows, each over its own run of
+// steps; it writes one partial N, D of shape [nP][KP] at slot `chunk`.
 struct FusedArgs {
   const float* Y;
   const uint8_t* M;            // nullptr: fully observed
-  const uint32_t* p_off;       // [nP] element offset of row p in Y
-  const uint32_t* q_off;       // [nQ] element offset of column q in Y
+  const uint32_t* p_off;       // [nP] Y offset of row p
   const float* L;              // L[p*ldL + k], k < K
   int ldL;
   int K;                       // true contraction width (<= KP)
-  int nP, nQ;
-  int npieces;
-  const float* piece[kMaxPieces];
-  const uint32_t* pidx[kMaxPieces];   // row index of column q in piece m; nullptr = q
-  int ldpiece[kMaxPieces];
-  int n_panels;                // ceil(nP / rows per wave)
-  int q_per_wave;              // multiple of 16
-  int n_chunks;                // q chunks = partial slots
+  int nP;
+  int nqo, nqi, nqis;          // nqis = ceil(nqi / 16)
+  int qi_ystride;              // Y stride of the qi mode
+  const uint32_t* qo_yoff;     // [nqo] Y offset of qo
+  const float* inner;
+  int ld_in, in_stride;
+  const uint32_t* in_base;     // [nqo] or nullptr (= 0)
+  int nouter;
+  const float* outer[2];
+  int ld_out[2];
+  const uint32_t* orow[2];     // [nqo]
+  int64_t n_steps;             // nqo * nqis
+  int n_panels;
+  int steps_per_wave;
+  int n_chunks;                // partial slots
   int n_wg;                    // grid size
-  int xcd_remap;               // 1: spread consecutive work over one XCD's slots
+  int xcd_remap;               // 1: consecutive work items share an XCD
   float* partN;                // [n_chunks][nP][KP]
   float* partD;                // [n_chunks][nP][KP] (unused when no_d)
-  double* loss_part;           // [n_wg] or nullptr
+  double* loss_part;           // [n_wg] (loss passes)
   int no_d;                    // D is a closed form (b = 1, no mask): skip it
-  int loss_only;               // only the loss is wanted
   float alpha, beta;           // for WK_GEN and the generic loss
-  float ab_inv, apb_inv;       // 1/(alpha*beta), 1/(alpha+beta) (generic loss)
-  int lk;                      // LossKind
+  float ab_inv, apb_inv;       // 1/(alpha*beta), 1/(alpha+beta)
+  int lk;                      // LossKind (generic weights only)
+  int full;                    // no ragged edges: K = KP, nqi % 16 = 0, nP % rows = 0
 };
 
 // Reduce the partials of a fused pass and apply the update (or store N_L/D_L).
@@ -78,7 +90,7 @@ struct UpdateArgs {
   const float* partN; const float* partD;
   int n_chunks, nP, K, KP;
   int no_d;
-  // closed-form D (no_d): D[p,k] = prod_m colsum(piece_m)[k]
+  // closed-form D (no_d): D[p,k] = prod_m colsum(piece_m)[k] (column-side pieces)
   int npieces;
   const float* piece[kMaxPieces];
   int ldpiece[kMaxPieces];
@@ -113,7 +125,8 @@ struct ApplyArgs {
 };
 
 // Launchers (kernels.hip).  Return 0 or a hipError_t value.
-int launch_fused(const FusedArgs& a, int KP, int wk, bool vecq, void* stream);
+// mode: 0 = N, D only; 1 = N, D and the loss; 2 = the loss only
+int launch_fused(const FusedArgs& a, int KP, int wk, bool vecq, int mode, void* stream);
 int launch_update(const UpdateArgs& a, float* dcol, void* stream);  // dcol: [K] scratch for a closed-form D
 int launch_einsum(const EinsumArgs& a, void* stream);
 int launch_apply(const ApplyArgs& a, void* stream);

@@ -361,12 +361,16 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
       }
       // ---- column side R: product of pieces, or one materialised piece
       bool kr = !q_empty && !qops.empty() && (int)qops.size() <= kMaxPieces;
+      const char qi_letter = q_empty ? 0 : bp2.Q.back();
+      int n_with_qi = 0;
       for (auto& t : qops) {
         std::string ob;
         for (char c : t.subs)
           if (m.out.find(c) != std::string::npos) ob.push_back(c);
         kr &= !ob.empty() && t.subs == ob + kappa;
+        n_with_qi += ob.find(qi_letter) != std::string::npos ? 1 : 0;
       }
+      kr &= n_with_qi == 1;  // one inner piece, the others indexed by qo only
       bp2.pieces.clear();
       if (kr) {
         for (auto& t : qops) {
@@ -404,9 +408,44 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
         }
         bp2.pieces.push_back(pc);
       }
+      {
+        std::set<char> seen;
+        bp2.pieces_disjoint = true;
+        for (auto& pc : bp2.pieces)
+          for (char c : pc.obs) bp2.pieces_disjoint &= seen.insert(c).second;
+      }
+      // ---- column decomposition q = (qo, qi)
+      bp2.qi = q_empty ? 0 : bp2.Q.back();
+      bp2.qo = q_empty ? std::string() : bp2.Q.substr(0, bp2.Q.size() - 1);
+      bp2.nqi = q_empty ? 1 : m.size[(unsigned char)bp2.qi];
+      bp2.nqo = bp2.nQ / bp2.nqi;
+      bp2.qi_ystride = 0;
+      if (!q_empty) {
+        int64_t st = 1;
+        for (int i = (int)m.out.size() - 1; i >= 0 && m.out[i] != bp2.qi; --i) st *= m.size[(unsigned char)m.out[i]];
+        bp2.qi_ystride = st;
+      }
+      bp2.outers.clear();
+      bp2.inner = 0;
+      bp2.in_stride = q_empty ? 0 : 1;
+      if (kr) {
+        for (int i = 0; i < (int)bp2.pieces.size(); ++i) {
+          const Piece& pc = bp2.pieces[i];
+          const size_t pos = pc.obs.find(bp2.qi);
+          if (pos == std::string::npos) {
+            bp2.outers.push_back(i);
+          } else {
+            bp2.inner = i;
+            int64_t st = 1;
+            for (size_t j = pos + 1; j < pc.obs.size(); ++j) st *= m.size[(unsigned char)pc.obs[j]];
+            bp2.in_stride = st;
+          }
+        }
+      }
       // ---- cost: fused MFMA work on padded tiles, plus the generic contractions
-      const int rows = KP == 64 ? 32 : 64;
-      const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nQ;
+      const int rows = KP == 16 ? 64 : KP == 32 ? 16 * kPT32 : 16;
+      const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nqo *
+                          std::ceil((double)bp2.nqi / 16) * 16;
       const double cost = Neff * 6.0 * KP + 16.0 * macs + 8.0 * mat_elems;
       if (best_cost < 0 || cost < best_cost) {
         best_cost = cost;
@@ -490,26 +529,44 @@ std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, con
   return t;
 }
 
-bool piece_is_identity(const Model& m, const std::string& Q, const std::string& obs) {
-  (void)m;
-  return obs == Q;
-}
 
 bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg) {
-  const int rows = bp.KP == 64 ? 32 : 64;
+  (void)m;
+  const int rows = bp.KP == 16 ? 64 : bp.KP == 32 ? 16 * kPT32 : 16;
   bp.n_panels = (int)((bp.nP + rows - 1) / rows);
-  const int64_t qsteps = (bp.nQ + 15) / 16;
+  const int64_t nqis = (bp.nqi + 15) / 16;
+  bp.n_steps = bp.nqo * nqis;
   int64_t chunks = std::max<int64_t>(1, (target_wg + bp.n_panels - 1) / bp.n_panels);
-  chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (qsteps + 3) / 4));
-  const int64_t steps_per_wave = (qsteps + 4 * chunks - 1) / (4 * chunks);
-  bp.q_per_wave = (int)(16 * steps_per_wave);
-  bp.n_chunks = (int)((bp.nQ + 4 * (int64_t)bp.q_per_wave - 1) / (4 * (int64_t)bp.q_per_wave));
+  chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (bp.n_steps + 3) / 4));
+  const int64_t spw = (bp.n_steps + 4 * chunks - 1) / (4 * chunks);
+  if (spw >= (int64_t(1) << 31)) return false;
+  bp.steps_per_wave = (int)spw;
+  bp.n_chunks = (int)((bp.n_steps + 4 * spw - 1) / (4 * spw));
   const int64_t nwg = (int64_t)bp.n_panels * bp.n_chunks;
   if (nwg >= (int64_t(1) << 31)) return false;
   bp.n_wg = (int)nwg;
   bp.xcd_remap = (bp.n_wg % 8 == 0 && bp.n_wg >= 64) ? 1 : 0;
-  const char last = m.out.back();
-  bp.vecq = bp.Q.find(last) != std::string::npos && m.size[(unsigned char)last] % 4 == 0;
+  bp.vecq = bp.qi_ystride == 1 && bp.nqi % 4 == 0;
+  return true;
+}
+
+std::vector<uint32_t> inner_base_table(const Model& m, const BlockPlan& bp) {
+  const Piece& pc = bp.pieces[bp.inner];
+  if (pc.factor < 0) {  // materialised rows: q = qo * nqi + qi
+    std::vector<uint32_t> t((size_t)bp.nqo);
+    for (int64_t i = 0; i < bp.nqo; ++i) t[(size_t)i] = (uint32_t)(i * bp.nqi);
+    return t;
+  }
+  return piece_rows_table(m, bp.qo, pc.obs);
+}
+
+std::vector<uint32_t> outer_row_table(const Model& m, const BlockPlan& bp, int piece) {
+  return piece_rows_table(m, bp.qo, bp.pieces[piece].obs);
+}
+
+bool all_zero(const std::vector<uint32_t>& t) {
+  for (auto v : t)
+    if (v) return false;
   return true;
 }
 
@@ -525,8 +582,9 @@ std::string describe_block(const Model& m, const BlockPlan& bp) {
       o << (i ? "," : "") << m.ops[bp.pieces[i].factor];
     o << ")";
   }
-  o << (bp.L_direct ? "" : " chain-back") << (bp.vecq ? " vecq" : "") << " grid=" << bp.n_wg
-    << " chunks=" << bp.n_chunks << " q/wave=" << bp.q_per_wave;
+  o << (bp.L_direct ? "" : " chain-back") << " qo={" << bp.qo << "} qi=" << (bp.qi ? bp.qi : '-')
+    << (bp.vecq ? " vecq" : "") << " grid=" << bp.n_wg << " chunks=" << bp.n_chunks
+    << " steps/wave=" << bp.steps_per_wave;
   return o.str();
 }
 

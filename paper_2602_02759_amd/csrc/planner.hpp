@@ -8,6 +8,11 @@
 
 namespace nnef {
 
+#ifndef NNEF_PT32
+#define NNEF_PT32 2
+#endif
+constexpr int kPT32 = NNEF_PT32;  // 16-row subtiles per wave for contraction width 32
+
 enum Status { ST_OK = 0, ST_PARSE = 1, ST_SHAPE = 2, ST_LOSS = 3, ST_ARG = 4, ST_DEVICE = 5,
               ST_NOMEM = 6, ST_UNSUPPORTED = 7 };
 
@@ -55,17 +60,28 @@ struct BlockPlan {
   std::vector<Step> L_prog;        // builds L (row side) from the current factors
   std::vector<Step> R_prog;        // builds a materialised R
   std::vector<Piece> pieces;
+  bool pieces_disjoint = true;     // no observed letter in two pieces (closed-form D valid)
   int ones_buf = -1;               // R = [1] when every mode is on the row side
   std::vector<Step> chainN, chainD;
   int NL_buf = -1, DL_buf = -1;    // [nP][K] reduced N_L, D_L
   int Nl_buf = -1, Dl_buf = -1;    // N_l, D_l shaped like operand l
+  // column multi-index q = (qo, qi): qi is the last column-side letter
+  std::string qo;
+  char qi = 0;
+  int64_t nqo = 1, nqi = 1;
+  int64_t qi_ystride = 0;          // Y stride of qi
+  int inner = 0;                   // piece holding qi (or the materialised buffer)
+  std::vector<int> outers;         // pieces indexed by qo only
+  int64_t in_stride = 1;           // row stride of qi inside the inner piece
   // launch geometry and device tables (filled by the ABI layer)
   bool vecq = false;
-  int n_panels = 0, q_per_wave = 0, n_chunks = 0, n_wg = 0;
+  int n_panels = 0, steps_per_wave = 0, n_chunks = 0, n_wg = 0;
+  int64_t n_steps = 0;
   int xcd_remap = 0;
   uint32_t* d_poff = nullptr;
-  uint32_t* d_qoff = nullptr;
-  uint32_t* d_pidx[kMaxPieces] = {nullptr, nullptr, nullptr};
+  uint32_t* d_qoyoff = nullptr;
+  uint32_t* d_inbase = nullptr;    // nullptr: all zero
+  uint32_t* d_orow[2] = {nullptr, nullptr};
 };
 
 Status parse_model(const std::string& s, Model& m, std::string& err);
@@ -77,7 +93,10 @@ std::vector<Step> plan_contraction(const Model& m, std::vector<TensorRef> in, co
 std::vector<int64_t> row_major_strides(const Model& m, const std::string& subs, int64_t inner);
 std::vector<uint32_t> offsets_table(const Model& m, const std::string& letters);
 std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, const std::string& obs);
-bool piece_is_identity(const Model& m, const std::string& Q, const std::string& obs);
+// Tables of the column decomposition (host side, uploaded by the ABI layer).
+std::vector<uint32_t> inner_base_table(const Model& m, const BlockPlan& bp);
+std::vector<uint32_t> outer_row_table(const Model& m, const BlockPlan& bp, int piece);
+bool all_zero(const std::vector<uint32_t>& t);
 bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg);
 std::string describe_block(const Model& m, const BlockPlan& bp);
 

@@ -15,7 +15,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnnef.so")
+LIB_PATH = os.environ.get("NNEF_LIB") or os.path.join(_HERE, "libnnef.so")
 _lib = None
 
 STATUS = {0: "NNEF_OK", 1: "NNEF_E_PARSE", 2: "NNEF_E_SHAPE", 3: "NNEF_E_LOSS_UNSUPPORTED",

@@ -66,6 +66,9 @@ def _case(name):
         return datagen.poisson_problem("icews", "ir,jr,ak,kr,tr->ijat",
                                        dict(i=12, j=12, a=5, t=9, r=6, k=2), 1.3, 1.0, seed=63,
                                        truth_shape=0.5, missing=0.1)
+    if name == "shared_letter":  # column-side pieces 'jr' and 'jkr' share j
+        return datagen.poisson_problem("shl", "ir,jr,jkr->ijk", dict(i=21, j=18, k=20, r=5),
+                                       1.0, 0.0, seed=67, truth_shape=0.5)
     if name == "rkl":
         return datagen.gamma_noise_problem("rkl", "ir,jr,kr->ijk", dict(i=20, j=24, k=18, r=6),
                                            0.0, 1.0, seed=64, missing=0.2)
@@ -80,7 +83,7 @@ def _case(name):
 
 SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_gen", "tucker_small",
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
-         "hellinger", "is"]
+         "hellinger", "is", "shared_letter"]
 
 
 @pytest.mark.parametrize("name", SMALL)
