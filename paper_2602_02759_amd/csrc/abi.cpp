@@ -45,6 +45,8 @@ struct nnef_plan_s {
   double* loss_part = nullptr;
   double* loss_tmp = nullptr;
   float* dcol = nullptr;
+  float* ypack = nullptr;          // data with missing entries stored as -1
+  int64_t n_data = 0;
   int max_wg = 0;
   std::vector<int64_t> numel;
   std::string description;
@@ -82,6 +84,7 @@ static void free_plan(nnef_plan_s* p) {
   if (p->loss_part) (void)hipFree(p->loss_part);
   if (p->loss_tmp) (void)hipFree(p->loss_tmp);
   if (p->dcol) (void)hipFree(p->dcol);
+  if (p->ypack) (void)hipFree(p->ypack);
   delete p;
 }
 
@@ -147,6 +150,7 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
                                   std::to_string(m.latent.size()) + " contracted letters");
   }
   int64_t N = 1;
+  p->n_data = 0;
   for (int i = 0; i < n_modes; ++i) {
     if (mode_sizes[i] <= 0) {
       free_plan(p);
@@ -166,6 +170,7 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
     }
     m.size[(unsigned char)m.latent[i]] = ranks[i];
   }
+  p->n_data = N;
   if (make_loss(alpha, beta, p->ls, err) != ST_OK) {
     free_plan(p);
     return fail(NNEF_E_LOSS_UNSUPPORTED, err);
@@ -230,7 +235,8 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
       hipMalloc((void**)&p->partD, std::max<size_t>(1, part_elems) * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&p->loss_part, std::max(1, p->max_wg) * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&p->loss_tmp, sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&p->dcol, 64 * sizeof(float)) != hipSuccess) {
+      hipMalloc((void**)&p->dcol, 64 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&p->ypack, (size_t)N * sizeof(float)) != hipSuccess) {
     free_plan(p);
     return fail(NNEF_E_NOMEM, "partial-sum allocation failed");
   }
@@ -314,11 +320,11 @@ static const float* piece_ptr(const nnef_plan_s* p, const Piece& pc, const float
 }
 
 static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const float* Y,
-                            const uint8_t* M, const float* const* factors) {
+                            bool masked, const float* const* factors) {
   FusedArgs a;
   std::memset(&a, 0, sizeof(a));
   a.Y = Y;
-  a.M = M;
+  a.masked = masked ? 1 : 0;
   a.p_off = bp.d_poff;
   a.L = bp.L_direct ? factors[bp.ell] : p->ws[bp.L_buf];
   a.ldL = bp.ldL;
@@ -349,7 +355,7 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.xcd_remap = bp.xcd_remap;
   a.partN = p->partN;
   a.partD = p->partD;
-  a.no_d = (p->ls.b_is_one() && M == nullptr && bp.pieces_disjoint) ? 1 : 0;
+  a.no_d = (p->ls.b_is_one() && !masked && bp.pieces_disjoint) ? 1 : 0;
   a.alpha = (float)p->ls.alpha;
   a.beta = (float)p->ls.beta;
   const double ab = p->ls.alpha * p->ls.beta, apb = p->ls.alpha + p->ls.beta;
@@ -377,12 +383,18 @@ nnef_status nnef_step(nnef_plan_t p, const float* Y, const uint8_t* M, float* co
     if (!factors[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
   const float* const* cf = factors;
+  const float* Yd = Y;
+  if (M && n_sweeps > 0) {
+    const int e = launch_pack(Y, M, p->ypack, p->n_data, s);
+    if (e) return hip_fail(e, "data packing launch");
+    Yd = p->ypack;
+  }
   for (int sw = 0; sw < n_sweeps; ++sw) {
     for (int l = 0; l < L; ++l) {
       const BlockPlan& bp = p->blocks[l];
       int e = run_side_prep(p, bp, cf, s);
       if (e) return hip_fail(e, "side-operand contraction launch");
-      FusedArgs fa = fused_args(p, bp, Y, M, cf);
+      FusedArgs fa = fused_args(p, bp, Yd, M != nullptr, cf);
       const bool want_loss = loss_trace && l == 0;
       fa.loss_part = want_loss ? p->loss_part : nullptr;
       hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -476,9 +488,16 @@ nnef_status nnef_loss_device(nnef_plan_t p, const float* Y, const uint8_t* M,
     if (!factors[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
   const BlockPlan& bp = p->blocks[0];
-  int e = run_side_prep(p, bp, factors, s);
+  int e = 0;
+  const float* Yd = Y;
+  if (M) {
+    e = launch_pack(Y, M, p->ypack, p->n_data, s);
+    if (e) return hip_fail(e, "data packing launch");
+    Yd = p->ypack;
+  }
+  e = run_side_prep(p, bp, factors, s);
   if (e) return hip_fail(e, "side-operand contraction launch");
-  FusedArgs fa = fused_args(p, bp, Y, M, factors);
+  FusedArgs fa = fused_args(p, bp, Yd, M != nullptr, factors);
   fa.loss_part = p->loss_part;
   e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, 2, s);
   if (e) return hip_fail(e, "loss pass launch");

@@ -170,6 +170,13 @@ struct Tile {
   static constexpr int RST = KP + 4;                            // LDS row stride (floats)
 };
 
+// Weight kinds that divide by yhat or raise it to a negative power need
+// yhat >= FLT_MIN (exact arithmetic keeps yhat > 0; FP32 may underflow).
+template <int WK>
+__device__ constexpr bool needs_floor() {
+  return WK == WK_KL || WK == WK_IS || WK == WK_GEN || WK == WK_RKL;
+}
+
 // Accumulator element (t, kt, r) is X^T[k = 16kt + 4g + r][p = 16t + c].  Waves
 // 1..3 stash theirs in LDS; wave 0 adds them in a fixed order and stores the
 // workgroup's partial rows.
@@ -205,7 +212,7 @@ __device__ __forceinline__ void store_partial(const f4 (&acc)[Tile<KP>::PT][Tile
 }
 
 template <int KP, int WK, bool VECQ, int MODE, bool FULL>
-__global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_pass(FusedArgs a) {
   using T = Tile<KP>;
   constexpr int PT = T::PT, ROWS = T::ROWS, KS = T::KS, KT = T::KT, RST = T::RST;
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
@@ -223,8 +230,7 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
   const int64_t s_beg = ((int64_t)chunk * 4 + wave) * a.steps_per_wave;
   const int64_t s_end = s_beg + a.steps_per_wave < a.n_steps ? s_beg + a.steps_per_wave : a.n_steps;
 
-  // ---- row side, in registers for the whole pass: lane holds L[p][g*KS + s]
-  float Lop[PT][KS];
+  // ---- row side: lane holds Lu[t][s] = L[p][g*KS + s] * u[g*KS + s], p = p0 + 16t + c
   uint32_t poff[PT];
   bool pval[PT];
 #pragma unroll
@@ -232,11 +238,6 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
     const int p = p0 + 16 * t + c;
     pval[t] = FULL || p < a.nP;
     poff[t] = pval[t] ? a.p_off[p] : 0u;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int k = g * KS + s;
-      Lop[t][s] = (pval[t] && k < a.K) ? a.L[(size_t)p * a.ldL + k] : 0.f;
-    }
   }
   // lane-constant kappa indices, clamped in range (out-of-range lanes are zeroed)
   int kA[KS], kB[KT];
@@ -254,48 +255,74 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
       accD[t][kt] = f4{0.f, 0.f, 0.f, 0.f};
     }
   double lsum = 0.0;
-  const bool has_mask = a.M != nullptr;
 
-  // ---- per-qo state: outer product u at this lane's kappa positions, inner base row
-  int cur_qo = -1;
-  float uA[KS], uB[KT];
-  uint32_t ibase = 0;
-  const bool vec_in = a.K == KP && (a.ld_in & 3) == 0;  // float4 loads of inner rows
-
-  auto load_qo = [&](int qo) {
+  // ---- outer factors: u[k] = prod_m outer_m[orow_m[qo]][k] is folded into the
+  // row operand (Lu = L * u) for the reconstruction, and into the contraction
+  // by accumulating per-qo partials tN, tD that are scaled by u and added to
+  // accN, accD whenever qo changes.  Column-side values stay raw loads.
+  float Lu[PT][KS];
+  f4 uN[KT];  // u at the accumulator rows k = 16 kt + 4g + r
+  f4 tN[PT][KT], tD[PT][KT];
+  const bool has_outer = a.nouter > 0;
+  auto zero_t = [&]() {
+#pragma unroll
+    for (int t = 0; t < PT; ++t)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        tN[t][kt] = f4{0.f, 0.f, 0.f, 0.f};
+        tD[t][kt] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  auto set_u = [&](int qo) {
+    float uA[KS];
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int p = p0 + 16 * t + c;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = g * KS + s;
+        Lu[t][s] = (pval[t] && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
+      }
+    }
 #pragma unroll
     for (int s = 0; s < KS; ++s) uA[s] = 1.f;
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) uB[kt] = 1.f;
+    for (int kt = 0; kt < KT; ++kt) uN[kt] = f4{1.f, 1.f, 1.f, 1.f};
     for (int m = 0; m < a.nouter; ++m) {
       const float* ob = a.outer[m];
       const uint32_t roff = a.orow[m][qo] * (uint32_t)a.ld_out[m];
-      if (FULL && (a.ld_out[m] & 3) == 0) {
 #pragma unroll
-        for (int s = 0; s < KS; s += 4) {
-          const f4 v = ldf4(ob, roff + g * KS + s);
-          uA[s] *= v[0];
-          uA[s + 1] *= v[1];
-          uA[s + 2] *= v[2];
-          uA[s + 3] *= v[3];
-        }
-      } else {
+      for (int s = 0; s < KS; ++s) uA[s] *= ldf(ob, roff + kA[s]);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) uA[s] *= ldf(ob, roff + kA[s]);
-      }
+      for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-      for (int kt = 0; kt < KT; ++kt) uB[kt] *= ldf(ob, roff + kB[kt]);
+        for (int r = 0; r < 4; ++r) uN[kt][r] *= ldf(ob, roff + min(16 * kt + 4 * g + r, a.K - 1));
     }
-    ibase = a.in_base ? a.in_base[qo] : 0u;
+#pragma unroll
+    for (int t = 0; t < PT; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) Lu[t][s] *= uA[s];
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int t = 0; t < PT; ++t)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        accN[t][kt] += uN[kt] * tN[t][kt];
+        if (!a.no_d) accD[t][kt] += uN[kt] * tD[t][kt];
+      }
+    zero_t();
   };
 
-  // column side of one step, in both MFMA layouts
+  // column side of one step, raw, in both MFMA layouts
   struct Cols {
-    float Ra[KS];     // R[qi0 + c][g*KS + s]
-    float Rb[KT][4];  // R[qi0 + 4g + r][16 kt + c]
+    float Ra[KS];     // C[qi0 + c][g*KS + s]
+    float Rb[KT][4];  // C[qi0 + 4g + r][16 kt + c]
   };
   const uint32_t ld_in = (uint32_t)a.ld_in, in_stride = (uint32_t)a.in_stride;
-  auto load_cols = [&](int qi0, Cols& d) {
+  const bool vec_in = a.K == KP && (a.ld_in & 3) == 0;  // float4 loads of inner rows
+  auto load_cols = [&](int qo, int qi0, Cols& d) {
+    const uint32_t ibase = a.in_base ? a.in_base[qo] : 0u;
     const int qa = qi0 + c;
     if constexpr (FULL) {
       const uint32_t ra = (ibase + (uint32_t)qa * in_stride) * ld_in;
@@ -304,25 +331,27 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
         for (int s = 0; s < KS; s += 4) {
           const f4 v = ldf4(a.inner, ra + g * KS + s);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) d.Ra[s + j] = v[j] * uA[s + j];
+          for (int j = 0; j < 4; ++j) d.Ra[s + j] = v[j];
         }
       } else {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) d.Ra[s] = ldf(a.inner, ra + g * KS + s) * uA[s];
+        for (int s = 0; s < KS; ++s) d.Ra[s] = ldf(a.inner, ra + g * KS + s);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const uint32_t rb = (ibase + (uint32_t)(qi0 + 4 * g + r) * in_stride) * ld_in;
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) d.Rb[kt][r] = ldf(a.inner, rb + 16 * kt + c) * uB[kt];
+        for (int kt = 0; kt < KT; ++kt) d.Rb[kt][r] = ldf(a.inner, rb + 16 * kt + c);
       }
     } else {
+      // ragged edges: clamp the address, zero the value
       const int qac = qa < a.nqi ? qa : a.nqi - 1;
       const uint32_t ra = (ibase + (uint32_t)qac * in_stride) * ld_in;
+      const bool va = qa < a.nqi;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const float v = ldf(a.inner, ra + kA[s]);
-        d.Ra[s] = (qa < a.nqi && g * KS + s < a.K) ? v * uA[s] : 0.f;
+        d.Ra[s] = (va && g * KS + s < a.K) ? v : 0.f;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -332,16 +361,15 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
           const float v = ldf(a.inner, rb + kB[kt]);
-          d.Rb[kt][r] = (qb < a.nqi && 16 * kt + c < a.K) ? v * uB[kt] : 0.f;
+          d.Rb[kt][r] = (qb < a.nqi && 16 * kt + c < a.K) ? v : 0.f;
         }
       }
     }
   };
 
-  // data and mask of one step (the HBM stream)
+  // data of one step (the HBM stream); a missing entry is stored as -1
   struct YM {
-    f4 y[PT];         // y[p0 + 16t + c][qi0 + 4g + r]
-    uint32_t m[PT];   // mask bytes, r = 0..3
+    f4 y[PT];  // y[p0 + 16t + c][qi0 + 4g + r]
   };
   const uint32_t qys = (uint32_t)a.qi_ystride;
   auto load_ym = [&](int qo, int qi0, YM& d) {
@@ -352,29 +380,22 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
       if constexpr (VECQ) {
         const bool ok = FULL || (pval[t] && q4 < a.nqi);
         const int q4c = FULL ? q4 : (q4 < a.nqi ? q4 : a.nqi - 4);
-        const uint32_t off = ybase + poff[t] + (uint32_t)q4c;
-        const f4 v = ldf4(a.Y, off);
-        const uint32_t mm = has_mask ? ldu32(a.M, off) : 0x01010101u;
-        d.y[t] = ok ? v : f4{0.f, 0.f, 0.f, 0.f};
-        d.m[t] = ok ? mm : 0u;
+        const f4 v = ldf4(a.Y, ybase + poff[t] + (uint32_t)q4c);
+        d.y[t] = ok ? v : f4{-1.f, -1.f, -1.f, -1.f};
       } else {
-        uint32_t mm = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int q = q4 + r;
           const bool ok = FULL || (pval[t] && q < a.nqi);
           const int qc = FULL ? q : (q < a.nqi ? q : a.nqi - 1);
-          const uint32_t off = ybase + poff[t] + (uint32_t)qc * qys;
-          const float v = ldf(a.Y, off);
-          const uint32_t mb = has_mask ? (uint32_t)a.M[off] : 1u;
-          d.y[t][r] = ok ? v : 0.f;
-          mm |= (ok ? mb : 0u) << (8 * r);
+          const float v = ldf(a.Y, ybase + poff[t] + (uint32_t)qc * qys);
+          d.y[t][r] = ok ? v : -1.f;
         }
-        d.m[t] = mm;
       }
     }
   };
 
+  const bool masked = a.masked != 0;  // else every entry is observed (y >= 0 by contract)
   auto compute = [&](const YM& ym, const Cols& cl) {
     // reconstruction tile, transposed: yh[t][r] = yhat[p0+16t+c][q = (qo, qi0+4g+r)]
     f4 yh[PT];
@@ -382,7 +403,7 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
     for (int t = 0; t < PT; ++t) {
       f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s2 = 0; s2 < KS; ++s2) acc = mfma4(cl.Ra[s2], Lop[t][s2], acc);
+      for (int s2 = 0; s2 < KS; ++s2) acc = mfma4(cl.Ra[s2], Lu[t][s2], acc);
       yh[t] = acc;
     }
     // masked weights (and loss)
@@ -391,9 +412,11 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
     for (int t = 0; t < PT; ++t) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const bool obs = (ym.m[t] >> (8 * r)) & 0xffu;
-        const float y = ym.y[t][r];
-        const float yhat = fmaxf(yh[t][r], FLT_MIN);
+        const float yv = ym.y[t][r];
+        const bool obs = !masked || yv >= 0.f;
+        const float y = masked ? fmaxf(yv, 0.f) : yv;
+        const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[t][r], FLT_MIN, FLT_MAX)
+                                             : yh[t][r];
         if constexpr (ND) {
           float xa, xb;
           ab_weights<WK>(y, yhat, a.alpha, a.beta, xa, xb);
@@ -407,73 +430,91 @@ __global__ __launch_bounds__(256) void fused_pass(FusedArgs a) {
       }
     }
     if constexpr (ND) {
-      // contractions: X^T[k][p] += sum_q R^T[k][q] W^T[q][p]
+      // contractions: X^T[k][p] += sum_q C^T[k][q] W^T[q][p]   (scaled by u at flush)
 #pragma unroll
       for (int t = 0; t < PT; ++t)
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accN[t][kt] = mfma4(cl.Rb[kt][r], wa[t][r], accN[t][kt]);
+          for (int r = 0; r < 4; ++r) tN[t][kt] = mfma4(cl.Rb[kt][r], wa[t][r], tN[t][kt]);
       if (!a.no_d) {
 #pragma unroll
         for (int t = 0; t < PT; ++t)
 #pragma unroll
           for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) accD[t][kt] = mfma4(cl.Rb[kt][r], wb[t][r], accD[t][kt]);
+            for (int r = 0; r < 4; ++r) tD[t][kt] = mfma4(cl.Rb[kt][r], wb[t][r], tD[t][kt]);
       }
     }
   };
 
   // ---- software pipeline: the HBM stream runs two steps ahead, the column
-  // side one step ahead; three-stage rings, unrolled so indices are static.
+  // side one step ahead; loads of a step are issued column side first so that
+  // waiting for them leaves the later Y loads in flight.  Three-stage rings,
+  // unrolled so that indices stay static.
   const int64_t nst = s_end > s_beg ? s_end - s_beg : 0;
-  int yq = 0, yqi = 0;
+  int q0 = 0, qis0 = 0;
   if (nst > 0) {
-    yq = (int)(s_beg / a.nqis);
-    yqi = (int)(s_beg - (int64_t)yq * a.nqis);
+    q0 = (int)(s_beg / a.nqis);
+    qis0 = (int)(s_beg - (int64_t)q0 * a.nqis);
   }
-  int cq = yq, cqi = yqi;
+  int yq = q0, yqi = qis0;   // next Y step to load
+  int cq = q0, cqi = qis0;   // next column step to load
+  int kq = q0, kqi = qis0;   // next step to compute
   auto adv = [&](int& qo, int& qis) {
     if (++qis == a.nqis) {
       qis = 0;
       ++qo;
     }
   };
+  zero_t();
+  int comp_qo = q0;
+  if (nst > 0) set_u(q0);
+  else {
+#pragma unroll
+    for (int t = 0; t < PT; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) Lu[t][s] = 0.f;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) uN[kt] = f4{0.f, 0.f, 0.f, 0.f};
+  }
   YM ym0, ym1, ym2;
   Cols c0, c1, c2;
   if (nst > 0) {
+    load_cols(cq, 16 * cqi, c0);
+    adv(cq, cqi);
     load_ym(yq, 16 * yqi, ym0);
     adv(yq, yqi);
-    load_qo(cq);
-    cur_qo = cq;
-    load_cols(16 * cqi, c0);
-    adv(cq, cqi);
   }
   if (nst > 1) {
     load_ym(yq, 16 * yqi, ym1);
     adv(yq, yqi);
   }
   auto step = [&](int64_t i, const YM& cy, YM& py, const Cols& cc, Cols& pc) {
+    if (i + 1 < nst) {
+      load_cols(cq, 16 * cqi, pc);
+      adv(cq, cqi);
+    }
     if (i + 2 < nst) {
       load_ym(yq, 16 * yqi, py);
       adv(yq, yqi);
     }
-    if (i + 1 < nst) {
-      if (cq != cur_qo) {
-        load_qo(cq);
-        cur_qo = cq;
+    if (kq != comp_qo) {  // entering a new qo: fold the finished one
+      if (has_outer) {
+        flush();
+        set_u(kq);
       }
-      load_cols(16 * cqi, pc);
-      adv(cq, cqi);
+      comp_qo = kq;
     }
     compute(cy, cc);
+    adv(kq, kqi);
   };
   for (int64_t i = 0; i < nst; i += 3) {
     step(i, ym0, ym2, c0, c1);
     if (i + 1 < nst) step(i + 1, ym1, ym0, c1, c2);
     if (i + 2 < nst) step(i + 2, ym2, ym1, c2, c0);
   }
+  flush();
 
   if constexpr (LOSS) {
     const double w = wave_sum(lsum);

@@ -137,6 +137,27 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
   a.out[ooff] = (float)acc;
 }
 
+// Missing entries become -1 (observed data are nonnegative); the value stored
+// at a missing entry is never read into arithmetic, only replaced.
+__global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Y,
+                                                   const uint8_t* __restrict__ M,
+                                                   float* __restrict__ Yp, int64_t n) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i + 3 < n) {
+    const v4 y = *reinterpret_cast<const v4*>(Y + i);
+    const uint32_t m = *reinterpret_cast<const uint32_t*>(M + i);
+    v4 o;
+    o[0] = (m & 0xffu) ? y[0] : -1.f;
+    o[1] = (m & 0xff00u) ? y[1] : -1.f;
+    o[2] = (m & 0xff0000u) ? y[2] : -1.f;
+    o[3] = (m & 0xff000000u) ? y[3] : -1.f;
+    *reinterpret_cast<v4*>(Yp + i) = o;
+  } else {
+    for (int64_t j = i; j < n; ++j) Yp[j] = M[j] ? Y[j] : -1.f;
+  }
+}
+
 __global__ __launch_bounds__(256) void zero_kernel(float* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
@@ -184,6 +205,14 @@ int launch_apply(const ApplyArgs& a, void* stream) {
 
 int launch_loss_final(const double* part, int n, double* out, void* stream) {
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, part, n, out);
+  return (int)hipGetLastError();
+}
+
+int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  const int64_t threads = (n + 3) / 4;
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, Y, M, Yp, n);
   return (int)hipGetLastError();
 }
 

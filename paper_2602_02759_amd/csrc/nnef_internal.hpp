@@ -52,8 +52,8 @@ struct LossSpec {
 // One workgroup = 4 waves on one panel of rows, each over its own run of
 // steps; it writes one partial N, D of shape [nP][KP] at slot `chunk`.
 struct FusedArgs {
-  const float* Y;
-  const uint8_t* M;            // nullptr: fully observed
+  const float* Y;              // data; with `masked`, a missing entry holds -1
+  int masked;                  // 0: every entry observed
   const uint32_t* p_off;       // [nP] Y offset of row p
   const float* L;              // L[p*ldL + k], k < K
   int ldL;
@@ -132,5 +132,7 @@ int launch_einsum(const EinsumArgs& a, void* stream);
 int launch_apply(const ApplyArgs& a, void* stream);
 int launch_loss_final(const double* part, int n, double* out, void* stream);
 int launch_zero(float* p, int64_t n, void* stream);
+// Yp[i] = mask[i] ? Y[i] : -1 (observed data are nonnegative).
+int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream);
 
 }  // namespace nnef
