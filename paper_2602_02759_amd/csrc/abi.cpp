@@ -332,7 +332,7 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.nP = (int)bp.nP;
   a.nqo = (int)bp.nqo;
   a.nqi = (int)bp.nqi;
-  a.nqis = (int)((bp.nqi + 15) / 16);
+  a.nqis = (int)((bp.nqi + bp.qstep - 1) / bp.qstep);
   a.qi_ystride = (int)bp.qi_ystride;
   a.qo_yoff = bp.d_qoyoff;
   const Piece& in = bp.pieces[bp.inner];
@@ -362,8 +362,8 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.ab_inv = ab != 0 ? (float)(1.0 / ab) : 0.f;
   a.apb_inv = apb != 0 ? (float)(1.0 / apb) : 0.f;
   a.lk = p->ls.lk;
-  const int rows = bp.KP == 16 ? 64 : bp.KP == 32 ? 16 * kPT32 : 16;
-  a.full = (bp.K == bp.KP && bp.nqi % 16 == 0 && bp.nP % rows == 0) ? 1 : 0;
+  a.full = (bp.K == bp.KP && bp.nqi % bp.qstep == 0 && bp.nP % bp.rows == 0 && bp.in_stride == 1 &&
+            bp.pieces[bp.inner].ld == bp.KP) ? 1 : 0;
   return a;
 }
 

@@ -170,11 +170,22 @@ struct Tile {
   static constexpr int RST = KP + 4;                            // LDS row stride (floats)
 };
 
+#ifndef NNEF_SCHED
+#define NNEF_SCHED 1
+#endif
+
 // Weight kinds that divide by yhat or raise it to a negative power need
 // yhat >= FLT_MIN (exact arithmetic keeps yhat > 0; FP32 may underflow).
 template <int WK>
 __device__ constexpr bool needs_floor() {
   return WK == WK_KL || WK == WK_IS || WK == WK_GEN || WK == WK_RKL;
+}
+
+// Weight kinds whose a(y, yhat) vanishes at y = 0 (alpha > 0), so a missing
+// entry stored as y = 0 needs no select for Wa.
+template <int WK>
+__device__ constexpr bool a_zero_at_zero() {
+  return WK == WK_KL || WK == WK_EUC || WK == WK_SQRT || WK == WK_IS;
 }
 
 // Accumulator element (t, kt, r) is X^T[k = 16kt + 4g + r][p = 16t + c].  Waves
@@ -396,56 +407,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   };
 
   const bool masked = a.masked != 0;  // else every entry is observed (y >= 0 by contract)
-  auto compute = [&](const YM& ym, const Cols& cl) {
-    // reconstruction tile, transposed: yh[t][r] = yhat[p0+16t+c][q = (qo, qi0+4g+r)]
-    f4 yh[PT];
+  // One step: reconstruction R(t), weights W(t), contractions ND(t) for the
+  // p subtiles t, ordered R(0) R(1)|W(0) ND(0)|W(1) ND(1) ... so that the
+  // weight arithmetic of one subtile issues in the shadow of the MFMAs of
+  // another (scheduling hints below keep that interleave).
+  auto recon = [&](int t, const Cols& cl) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < PT; ++t) {
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int s2 = 0; s2 < KS; ++s2) acc = mfma4(cl.Ra[s2], Lu[t][s2], acc);
+    return acc;
+  };
+  auto weights = [&](int t, const YM& ym, const f4& yh, f4& wa, f4& wb) {
 #pragma unroll
-      for (int s2 = 0; s2 < KS; ++s2) acc = mfma4(cl.Ra[s2], Lu[t][s2], acc);
-      yh[t] = acc;
-    }
-    // masked weights (and loss)
-    f4 wa[PT], wb[PT];
-#pragma unroll
-    for (int t = 0; t < PT; ++t) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float yv = ym.y[t][r];
-        const bool obs = !masked || yv >= 0.f;
-        const float y = masked ? fmaxf(yv, 0.f) : yv;
-        const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[t][r], FLT_MIN, FLT_MAX)
-                                             : yh[t][r];
-        if constexpr (ND) {
-          float xa, xb;
-          ab_weights<WK>(y, yhat, a.alpha, a.beta, xa, xb);
-          wa[t][r] = obs ? xa : 0.f;
-          wb[t][r] = obs ? xb : 0.f;
-        }
-        if constexpr (LOSS) {
-          const float l = ab_loss<WK>(obs ? y : 1.f, obs ? yhat : 1.f, a);
-          lsum += obs ? (double)l : 0.0;
-        }
+    for (int r = 0; r < 4; ++r) {
+      const float yv = ym.y[t][r];
+      const bool obs = !masked || yv >= 0.f;
+      const float y = masked ? fmaxf(yv, 0.f) : yv;
+      const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[r], FLT_MIN, FLT_MAX) : yh[r];
+      if constexpr (ND) {
+        float xa, xb;
+        ab_weights<WK>(y, yhat, a.alpha, a.beta, xa, xb);
+        wa[r] = obs ? xa : 0.f;
+        wb[r] = obs ? xb : 0.f;
+      }
+      if constexpr (LOSS) {
+        const float l = ab_loss<WK>(obs ? y : 1.f, obs ? yhat : 1.f, a);
+        lsum += obs ? (double)l : 0.0;
       }
     }
+  };
+  auto contract = [&](int t, const Cols& cl, const f4& wa, const f4& wb) {
     if constexpr (ND) {
-      // contractions: X^T[k][p] += sum_q C^T[k][q] W^T[q][p]   (scaled by u at flush)
+      // X^T[k][p] += sum_q C^T[k][q] W^T[q][p]   (scaled by u at flush)
 #pragma unroll
-      for (int t = 0; t < PT; ++t)
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tN[t][kt] = mfma4(cl.Rb[kt][r], wa[r], tN[t][kt]);
+      if (!a.no_d) {
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) tN[t][kt] = mfma4(cl.Rb[kt][r], wa[t][r], tN[t][kt]);
-      if (!a.no_d) {
-#pragma unroll
-        for (int t = 0; t < PT; ++t)
-#pragma unroll
-          for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tD[t][kt] = mfma4(cl.Rb[kt][r], wb[t][r], tD[t][kt]);
+          for (int r = 0; r < 4; ++r) tD[t][kt] = mfma4(cl.Rb[kt][r], wb[r], tD[t][kt]);
       }
     }
+  };
+  auto compute = [&](const YM& ym, const Cols& cl) {
+    f4 yh[PT], wa[PT], wb[PT];
+    yh[0] = recon(0, cl);
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      if (t + 1 < PT) yh[t + 1] = recon(t + 1, cl);
+      weights(t, ym, yh[t], wa[t], wb[t]);
+      contract(t, cl, wa[t], wb[t]);
+    }
+#if NNEF_SCHED
+    // MFMA/VALU interleave: R(0); then per subtile its successor's R (KS
+    // MFMAs) or its own ND (8 KT MFMAs) alternating with the weight VALU.
+    __builtin_amdgcn_sched_group_barrier(0x008, KS, 0);
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int nm = (t + 1 < PT ? KS : 0) + (ND ? 8 * KT : 0);
+#pragma unroll
+      for (int j = 0; j < nm; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+      }
+    }
+#endif
   };
 
   // ---- software pipeline: the HBM stream runs two steps ahead, the column

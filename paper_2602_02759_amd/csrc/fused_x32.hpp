@@ -1,0 +1,434 @@
+// Fused pass for contraction width 32 on v_mfma_f32_32x32x2_f32.
+//
+// Same computation as fused_pass in fused_impl.hpp (one block update's pass
+// over Y: reconstruction tile, masked (alpha, beta) weights, numerator and
+// denominator contractions), with 32 x 32 tiles: this MFMA form sustains the
+// full FP32 matrix rate of the chip, the 16x16x4 form does not.
+//
+// MFMA layout (32x32x2): lane l = 32*g + c supplies A[row c][k g] and
+// B[k g][col c]; the accumulator register v holds C[row 8(v/4) + 4g + v%4][col c].
+// The tile is computed transposed, Yhat^T[q][p], so each lane owns one p and
+// 16 q values, which feed the contraction MFMAs directly as the B operand
+// (K = q).  A wave covers 32 rows p and steps of 32 columns q.
+#pragma once
+#include "fused_impl.hpp"
+
+namespace nnef {
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f16v mfma32(float a, float b, const f16v& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <int WK, bool VECQ, int MODE, bool FULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_x32(
+    FusedArgs a) {
+  constexpr int KP = 32, ROWS = 32, RST = KP + 4;
+  constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
+  // Y ring for the direct-to-LDS prefetch of full tiles: kStages stages of 4 KB
+  // per wave; after the main loop the same memory holds the partial reduction.
+  constexpr int kStages = 4;
+  constexpr int kRing = FULL ? 4 * kStages * 256 : 0;     // f4 elements
+  constexpr int kRed = ND ? 3 * ROWS * RST / 4 : 1;       // f4 elements
+  __shared__ f4 lds4[kRing > kRed ? kRing : kRed];
+  __shared__ double lred[4];
+  float* red = reinterpret_cast<float*>(lds4);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 5, c = lane & 31;
+  int b = blockIdx.x;
+  if (a.xcd_remap) b = (b & 7) * (a.n_wg >> 3) + (b >> 3);
+  const int panel = b % a.n_panels, chunk = b / a.n_panels;
+  const int p0 = panel * ROWS;
+  const int64_t s_beg = ((int64_t)chunk * 4 + wave) * a.steps_per_wave;
+  const int64_t s_end = s_beg + a.steps_per_wave < a.n_steps ? s_beg + a.steps_per_wave : a.n_steps;
+
+  const int p = p0 + c;
+  const bool pval = FULL || p < a.nP;
+  const uint32_t poff = pval ? a.p_off[p] : 0u;
+  const bool masked = a.masked != 0;
+
+  f16v accN = {}, accD = {};
+  double lsum = 0.0;
+
+  // ---- per-qo state: Lu[s] = L[p][16g + s] * u[16g + s] (reconstruction B operand),
+  // ul = u[c] (scales the contraction A operand, whose row is k = c)
+  float Lu[16];
+  float ul = 1.f;
+  auto set_u = [&](int qo) {
+    float uA[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) uA[s] = 1.f;
+    ul = 1.f;
+    for (int m = 0; m < a.nouter; ++m) {
+      const float* ob = a.outer[m];
+      const uint32_t roff = a.orow[m][qo] * (uint32_t)a.ld_out[m];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) uA[s] *= ldf(ob, roff + min(16 * g + s, a.K - 1));
+      ul *= ldf(ob, roff + min(c, a.K - 1));
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = 16 * g + s;
+      const float lv = (pval && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
+      Lu[s] = lv * uA[s];
+    }
+  };
+
+  // ---- column side of one step (raw inner rows).  Every load is a
+  // wave-uniform pointer plus a loop-invariant lane offset, so a step's
+  // addressing is scalar arithmetic only.
+  struct Cols {
+    float Ra[16];  // C[qi0 + c][16g + s]             (A of the reconstruction)
+    float Rb[16];  // C[qi0 + 8(v/4) + 4g + v%4][c]   (A of N and D, MFMA step v)
+  };
+  const uint32_t ld_in = (uint32_t)a.ld_in, in_stride = (uint32_t)a.in_stride;
+  // full tiles: inner rows are 32 floats apart (K = ld = 32, in_stride = 1), so
+  // every offset inside a step is a compile-time immediate on one base pointer
+  const uint32_t offA = (uint32_t)c * KP + 16u * g;         // lane part of Ra addresses
+  const uint32_t offB = (uint32_t)(4 * g) * KP + (uint32_t)c;  // lane part of Rb addresses
+  auto load_cols = [&](uint32_t ibase, int qi0, Cols& d) {
+    if constexpr (FULL) {
+      const float* base = a.inner + (size_t)(ibase + (uint32_t)qi0) * KP;
+#pragma unroll
+      for (int s = 0; s < 16; s += 4) {
+        const f4 v = ldf4(base, offA + s);
+        d.Ra[s] = v[0];
+        d.Ra[s + 1] = v[1];
+        d.Ra[s + 2] = v[2];
+        d.Ra[s + 3] = v[3];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) d.Rb[v] = ldf(base, offB + (uint32_t)(8 * (v >> 2) + (v & 3)) * KP);
+    } else {
+      const int qa = qi0 + c;
+      const bool va = qa < a.nqi;
+      const uint32_t ra = (ibase + (uint32_t)(va ? qa : a.nqi - 1) * in_stride) * ld_in;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int k = 16 * g + s;
+        const float v = ldf(a.inner, ra + (uint32_t)min(k, a.K - 1));
+        d.Ra[s] = (va && k < a.K) ? v : 0.f;
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int qb = qi0 + 8 * (v >> 2) + 4 * g + (v & 3);
+        const bool vb = qb < a.nqi && c < a.K;
+        const float x = ldf(a.inner, (ibase + (uint32_t)(qb < a.nqi ? qb : a.nqi - 1) * in_stride) * ld_in +
+                                         (uint32_t)min(c, a.K - 1));
+        d.Rb[v] = vb ? x : 0.f;
+      }
+    }
+  };
+
+  // ---- data of one step: y[q0 + 8(v/4) + 4g + v%4][p]; a missing entry holds -1
+  struct YM {
+    f4 y[4];
+  };
+  const uint32_t qys = (uint32_t)a.qi_ystride;
+  const uint32_t offY = poff + 4u * g;               // lane part of Y addresses (VECQ)
+  const uint32_t offYs = poff + (uint32_t)(4 * g) * qys;  // lane part of Y addresses (strided q)
+  auto load_ym = [&](uint32_t ybase, int qi0, YM& d) {
+#pragma unroll
+    for (int bq = 0; bq < 4; ++bq) {
+      const int q4 = qi0 + 8 * bq + 4 * g;
+      if constexpr (VECQ) {
+        if constexpr (FULL) {
+          d.y[bq] = ldf4(a.Y + ybase + (uint32_t)qi0, offY + 8u * bq);
+        } else {
+          const bool ok = pval && q4 < a.nqi;
+          const int q4c = q4 < a.nqi ? q4 : a.nqi - 4;
+          const f4 v = ldf4(a.Y, ybase + poff + (uint32_t)q4c);
+          d.y[bq] = ok ? v : f4{-1.f, -1.f, -1.f, -1.f};
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = q4 + r;
+          if constexpr (FULL) {
+            d.y[bq][r] = ldf(a.Y + ybase + (size_t)(qi0 + 8 * bq + r) * qys, offYs);
+          } else {
+            const bool ok = pval && q < a.nqi;
+            const float v = ldf(a.Y, ybase + poff + (uint32_t)(q < a.nqi ? q : a.nqi - 1) * qys);
+            d.y[bq][r] = ok ? v : -1.f;
+          }
+        }
+      }
+    }
+  };
+
+  // ---- direct-to-LDS prefetch of Y for full tiles.  Every lane moves its own
+  // 16 B (VECQ) or 4 B (strided q) and reads back exactly what it moved, so
+  // the ring is private to the wave and needs no barrier; completion is a
+  // vmcnt wait (the LDS DMA counts as a vector memory operation).
+  f4* ring = lds4 + wave * (kStages * 256);
+  auto dma_ym = [&](uint32_t ybase, int qi0, int stage) {
+    if constexpr (FULL) {
+      f4* st = ring + stage * 256;
+      if constexpr (VECQ) {
+        const float* src = a.Y + ybase + (uint32_t)qi0 + offY;
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq)
+          __builtin_amdgcn_global_load_lds((const void*)(src + 8 * bq),
+                                           (__attribute__((address_space(3))) void*)(st + 64 * bq), 16, 0, 0);
+      } else {
+        float* stf = reinterpret_cast<float*>(st);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const float* src = a.Y + ybase + (size_t)(qi0 + 8 * (v >> 2) + (v & 3)) * qys + offYs;
+          __builtin_amdgcn_global_load_lds((const void*)src,
+                                           (__attribute__((address_space(3))) void*)(stf + 64 * v), 4, 0, 0);
+        }
+      }
+    }
+  };
+  auto read_ym = [&](int stage, YM& d) {
+    const f4* st = ring + stage * 256;
+    if constexpr (VECQ) {
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) d.y[bq] = st[64 * bq + lane];
+    } else {
+      const float* stf = reinterpret_cast<const float*>(st);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) d.y[v >> 2][v & 3] = stf[64 * v + lane];
+    }
+  };
+
+  auto compute = [&](const YM& ym, const Cols& cl) {
+    f16v yh = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) yh = mfma32(cl.Ra[s], Lu[s], yh);
+    f16v wa, wb;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float yv = ym.y[v >> 2][v & 3];
+      const bool obs = !masked || yv >= 0.f;
+      // a missing entry (-1) becomes 0: a(0, yhat) = 0 for alpha > 0
+      const float y = masked ? __builtin_amdgcn_fmed3f(yv, 0.f, FLT_MAX) : yv;
+      const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[v], FLT_MIN, FLT_MAX) : yh[v];
+      if constexpr (ND) {
+        float xa, xb;
+        ab_weights<WK>(y, yhat, a.alpha, a.beta, xa, xb);
+        wa[v] = (a_zero_at_zero<WK>() || obs) ? xa : 0.f;
+        wb[v] = obs ? xb : 0.f;
+      }
+      if constexpr (LOSS) {
+        const float l = ab_loss<WK>(obs ? y : 1.f, obs ? yhat : 1.f, a);
+        lsum += obs ? (double)l : 0.0;
+      }
+    }
+    if constexpr (ND) {
+      // N^T[k][p] += sum_q (u[k] C[q][k]) W^T[q][p]
+      float rb[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) rb[v] = cl.Rb[v] * ul;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) accN = mfma32(rb[v], wa[v], accN);
+      if (!a.no_d) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accD = mfma32(rb[v], wb[v], accD);
+      }
+    }
+  };
+
+  // ---- software pipeline: column side and data one step ahead (two-stage rings);
+  // per-qo bases are refreshed only when the load iterator enters a new qo
+  const int64_t nst = s_end > s_beg ? s_end - s_beg : 0;
+  int q0 = 0, qis0 = 0;
+  if (nst > 0) {
+    q0 = (int)(s_beg / a.nqis);
+    qis0 = (int)(s_beg - (int64_t)q0 * a.nqis);
+  }
+  int lq = q0, lqi = qis0;  // next step to load
+  int kq = q0, kqi = qis0;  // next step to compute
+  uint32_t ybase = 0, ibase = 0;
+  auto set_bases = [&](int qo) {
+    ybase = a.qo_yoff[qo];
+    ibase = a.in_base ? a.in_base[qo] : 0u;
+  };
+  auto adv_load = [&]() {
+    if (++lqi == a.nqis) {
+      lqi = 0;
+      ++lq;
+      set_bases(lq);
+    }
+  };
+  int comp_qo = q0;
+  if (nst > 0) {
+    set_bases(q0);
+    // full tiles issue the first data moves before the factor rows below, so
+    // their latencies overlap (set_u runs inside the pipelined branch)
+    if constexpr (!FULL) set_u(q0);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) Lu[s] = 0.f;
+  }
+  if constexpr (FULL) {
+   if (nst > 0) {
+    // Y: direct-to-LDS ring, kStages - 1 steps ahead; column side: registers,
+    // one step ahead.  Issue order per step: Y DMA (nY ops), then column loads
+    // (nC ops).  Before reading stage j at least kWait ops issued after its DMA
+    // exist in every non-tail step, so vmcnt <= kWait implies it landed.
+    constexpr int nY = VECQ ? 4 : 16, nC = 4 + 16;
+    constexpr int kMin = (kStages - 1) * nY + 2 * nC < nC + (kStages - 1) * (nY + nC)
+                             ? (kStages - 1) * nY + 2 * nC
+                             : nC + (kStages - 1) * (nY + nC);
+    constexpr int kWait = kMin < 63 ? kMin : 63;  // vmcnt holds 6 bits; smaller is safe
+    constexpr int kWaitImm = (kWait & 15) | ((kWait >> 4) << 14) | (7 << 4) | (15 << 8);
+    constexpr int kWait0 = (7 << 4) | (15 << 8);  // vmcnt(0)
+    (void)kWait0;
+    int dq = lq, dqi = lqi;  // next Y step to move (lq, lqi: next column step)
+    uint32_t dybase = ybase;
+    auto adv_dma = [&]() {
+      if (++dqi == a.nqis) {
+        dqi = 0;
+        ++dq;
+        dybase = a.qo_yoff[dq];
+      }
+    };
+    // Every path issues the same loads: past the end of the range the
+    // iterators stay on the last step and re-issue it (an L2 hit).  Equal
+    // counts keep the waitcnt analysis exact at every join, so prefetches
+    // stay in flight.
+    Cols c0, c1;
+    for (int j = 0; j < kStages - 1; ++j) {
+      dma_ym(dybase, 32 * dqi, j);
+      if (j + 1 < nst) adv_dma();
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    load_cols(ibase, 32 * lqi, c0);
+    if (nst > 1) adv_load();
+    set_u(q0);
+    auto stepf = [&](int64_t i, const Cols& cc, Cols& pc) {
+      dma_ym(dybase, 32 * dqi, (int)((i + kStages - 1) % kStages));
+      if (i + kStages < nst) adv_dma();
+      __builtin_amdgcn_sched_barrier(0);  // keep the issue order: Y DMA, then column loads
+      load_cols(ibase, 32 * lqi, pc);
+      if (i + 2 < nst) adv_load();
+      if (kq != comp_qo) {
+        if (a.nouter > 0) set_u(kq);
+        comp_qo = kq;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(kWaitImm);
+      __builtin_amdgcn_sched_barrier(0);
+      YM cy;
+      read_ym((int)(i % kStages), cy);
+      compute(cy, cc);
+      if (++kqi == a.nqis) {
+        kqi = 0;
+        ++kq;
+      }
+    };
+    for (int64_t i = 0; i < nst; i += 2) {
+      stepf(i, c0, c1);
+      if (i + 1 < nst) stepf(i + 1, c1, c0);
+    }
+    __builtin_amdgcn_s_waitcnt(kWait0);  // retire the trailing re-issued loads
+   }
+    __syncthreads();  // the ring memory is reused for the partial reduction
+  } else {
+    YM y0, y1;
+    Cols c0, c1;
+    if (nst > 0) {
+      load_cols(ibase, 32 * lqi, c0);
+      load_ym(ybase, 32 * lqi, y0);
+      if (nst > 1) adv_load();
+    }
+    auto step = [&](int64_t i, const YM& cy, YM& py, const Cols& cc, Cols& pc) {
+      if (i + 1 < nst) {
+        load_cols(ibase, 32 * lqi, pc);
+        load_ym(ybase, 32 * lqi, py);
+        if (i + 2 < nst) adv_load();
+      }
+      if (kq != comp_qo) {
+        if (a.nouter > 0) set_u(kq);
+        comp_qo = kq;
+      }
+      compute(cy, cc);
+      if (++kqi == a.nqis) {
+        kqi = 0;
+        ++kq;
+      }
+    };
+    for (int64_t i = 0; i < nst; i += 2) {
+      step(i, y0, y1, c0, c1);
+      if (i + 1 < nst) step(i + 1, y1, y0, c1, c0);
+    }
+  }
+
+  if constexpr (LOSS) {
+    const double w = wave_sum(lsum);
+    if (lane == 0) lred[wave] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+  }
+  if constexpr (ND) {
+    // accumulator register v holds X^T[k = 8(v/4) + 4g + v%4][p = p0 + c]; waves
+    // 1..3 stash theirs, wave 0 adds them in a fixed order and stores the partial
+    auto store = [&](const f16v& acc, float* dst) {
+      if (wave > 0) {
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq)
+          *reinterpret_cast<f4*>(&red[(wave - 1) * ROWS * RST + c * RST + 8 * bq + 4 * g]) =
+              f4{acc[4 * bq], acc[4 * bq + 1], acc[4 * bq + 2], acc[4 * bq + 3]};
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) {
+          f4 v = f4{acc[4 * bq], acc[4 * bq + 1], acc[4 * bq + 2], acc[4 * bq + 3]};
+#pragma unroll
+          for (int w = 0; w < 3; ++w)
+            v += *reinterpret_cast<const f4*>(&red[w * ROWS * RST + c * RST + 8 * bq + 4 * g]);
+          if (p < a.nP) *reinterpret_cast<f4*>(&dst[((size_t)chunk * a.nP + p) * KP + 8 * bq + 4 * g]) = v;
+        }
+      }
+      __syncthreads();
+    };
+    store(accN, a.partN);
+    if (!a.no_d) store(accD, a.partD);
+  }
+}
+
+template <int WK, bool VECQ, int MODE>
+int launch_x32_t(const FusedArgs& a, hipStream_t s) {
+  if (a.full)
+    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, true>), dim3(a.n_wg), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, false>), dim3(a.n_wg), dim3(256), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+template <int WK>
+int launch_x32_w(const FusedArgs& a, bool vecq, int mode, hipStream_t s) {
+  if (vecq) {
+    switch (mode) {
+      case 0: return launch_x32_t<WK, true, 0>(a, s);
+      case 1: return launch_x32_t<WK, true, 1>(a, s);
+      default: return launch_x32_t<WK, true, 2>(a, s);
+    }
+  }
+  switch (mode) {
+    case 0: return launch_x32_t<WK, false, 0>(a, s);
+    case 1: return launch_x32_t<WK, false, 1>(a, s);
+    default: return launch_x32_t<WK, false, 2>(a, s);
+  }
+}
+
+int launch_x32(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
+  switch (wk) {
+    case WK_KL: return launch_x32_w<WK_KL>(a, vecq, mode, s);
+    case WK_EUC: return launch_x32_w<WK_EUC>(a, vecq, mode, s);
+    case WK_SQRT: return launch_x32_w<WK_SQRT>(a, vecq, mode, s);
+    case WK_IS: return launch_x32_w<WK_IS>(a, vecq, mode, s);
+    case WK_GEN: return launch_x32_w<WK_GEN>(a, vecq, mode, s);
+    default: return launch_x32_w<WK_RKL>(a, vecq, mode, s);
+  }
+}
+
+}  // namespace
+}  // namespace nnef

@@ -69,9 +69,27 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, const float* 
   const int p = valid ? (int)(idx / a.K) : 0, k = valid ? (int)(idx % a.K) : 0;
   double N = 0.0, D = 0.0;
   if (valid) {
-    for (int ch = w; ch < a.n_chunks; ch += 4) N += a.partN[((size_t)ch * a.nP + p) * a.KP + k];
-    if (!a.no_d)
-      for (int ch = w; ch < a.n_chunks; ch += 4) D += a.partD[((size_t)ch * a.nP + p) * a.KP + k];
+    // eight independent partial sums keep eight loads in flight per lane;
+    // they are combined in a fixed order (deterministic)
+    const size_t stride = (size_t)a.nP * a.KP;
+    const float* pn = a.partN + (size_t)p * a.KP + k;
+    const float* pd = a.partD + (size_t)p * a.KP + k;
+    double sn[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int ch = w;
+    for (; ch + 28 < a.n_chunks; ch += 32) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sn[j] += pn[(size_t)(ch + 4 * j) * stride];
+      if (!a.no_d) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sd[j] += pd[(size_t)(ch + 4 * j) * stride];
+      }
+    }
+    for (; ch < a.n_chunks; ch += 4) {
+      sn[0] += pn[(size_t)ch * stride];
+      if (!a.no_d) sd[0] += pd[(size_t)ch * stride];
+    }
+    N = ((sn[0] + sn[1]) + (sn[2] + sn[3])) + ((sn[4] + sn[5]) + (sn[6] + sn[7]));
+    D = ((sd[0] + sd[1]) + (sd[2] + sd[3])) + ((sd[4] + sd[5]) + (sd[6] + sd[7]));
   }
   sN[w][lane] = N;
   sD[w][lane] = D;

@@ -443,9 +443,10 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
         }
       }
       // ---- cost: fused MFMA work on padded tiles, plus the generic contractions
-      const int rows = KP == 16 ? 64 : KP == 32 ? 16 * kPT32 : 16;
+      const int rows = KP == 16 ? 64 : KP == 32 ? (kX32 ? 32 : 16 * kPT32) : 16;
+      const int qstep = (KP == 32 && kX32) ? 32 : 16;
       const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nqo *
-                          std::ceil((double)bp2.nqi / 16) * 16;
+                          std::ceil((double)bp2.nqi / qstep) * qstep;
       const double cost = Neff * 6.0 * KP + 16.0 * macs + 8.0 * mat_elems;
       if (best_cost < 0 || cost < best_cost) {
         best_cost = cost;
@@ -532,9 +533,11 @@ std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, con
 
 bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg) {
   (void)m;
-  const int rows = bp.KP == 16 ? 64 : bp.KP == 32 ? 16 * kPT32 : 16;
+  bp.qstep = (bp.KP == 32 && kX32) ? 32 : 16;
+  bp.rows = bp.KP == 16 ? 64 : bp.KP == 32 ? (kX32 ? 32 : 16 * kPT32) : 16;
+  const int rows = bp.rows;
   bp.n_panels = (int)((bp.nP + rows - 1) / rows);
-  const int64_t nqis = (bp.nqi + 15) / 16;
+  const int64_t nqis = (bp.nqi + bp.qstep - 1) / bp.qstep;
   bp.n_steps = bp.nqo * nqis;
   int64_t chunks = std::max<int64_t>(1, (target_wg + bp.n_panels - 1) / bp.n_panels);
   chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (bp.n_steps + 3) / 4));

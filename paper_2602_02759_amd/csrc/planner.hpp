@@ -12,6 +12,10 @@ namespace nnef {
 #define NNEF_PT32 2
 #endif
 constexpr int kPT32 = NNEF_PT32;  // 16-row subtiles per wave for contraction width 32
+#ifndef NNEF_X32
+#define NNEF_X32 1
+#endif
+constexpr bool kX32 = NNEF_X32 != 0;  // width 32 runs on 32x32x2 MFMA tiles (32 rows, 32-wide q steps)
 
 enum Status { ST_OK = 0, ST_PARSE = 1, ST_SHAPE = 2, ST_LOSS = 3, ST_ARG = 4, ST_DEVICE = 5,
               ST_NOMEM = 6, ST_UNSUPPORTED = 7 };
@@ -74,6 +78,8 @@ struct BlockPlan {
   std::vector<int> outers;         // pieces indexed by qo only
   int64_t in_stride = 1;           // row stride of qi inside the inner piece
   // launch geometry and device tables (filled by the ABI layer)
+  int qstep = 16;                  // columns per step of the fused pass
+  int rows = 64;                   // rows per wave (panel height)
   bool vecq = false;
   int n_panels = 0, steps_per_wave = 0, n_chunks = 0, n_wg = 0;
   int64_t n_steps = 0;
