@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--beta", type=float, default=1.0)
     ap.add_argument("--n", type=int, default=256, help="mode size")
     ap.add_argument("--rank", type=int, default=32)
+    ap.add_argument("--prec", choices=("fp32", "bf16", "fp16"), default="fp32",
+                    help="input precision of the N/D contractions")
     ap.add_argument("--cpu-sweeps", type=int, default=3,
                     help="oracle sweeps timed for the CPU baseline (0 disables)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -88,7 +90,7 @@ def main():
     Y = torch.from_numpy(p.Y).to(dev)
     M = torch.from_numpy(p.M).to(dev)
     f = [torch.from_numpy(np.maximum(t, 1e-10)).to(dev) for t in p.init]
-    plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta)
+    plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, prec=args.prec)
     stream = torch.cuda.current_stream()
 
     if args.copy_calibration:

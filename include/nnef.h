@@ -59,8 +59,12 @@ typedef enum {
   NNEF_E_UNSUPPORTED = 7       /* a model the planner cannot lower              */
 } nnef_status;
 
-/* Input precision of the MFMA contractions.  Weights, ratios, powers, the
- * update and the loss terms are always float32; loss sums are float64. */
+/* Input precision of the numerator and denominator contractions (the einsums
+ * with a(Y,Yhat) and b(Y,Yhat) of Algorithm 1) on MFMA, with FP32
+ * accumulation.  It applies to blocks whose contraction width is 17..32; other
+ * widths, the reconstruction Yhat, the weights, the ratio N/D, the power and
+ * the update, and the loss terms are float32; loss sums are float64.
+ * nnef_plan_describe reports the precision chosen for every block. */
 typedef enum { NNEF_FP32 = 0, NNEF_BF16 = 1, NNEF_FP16 = 2 } nnef_prec;
 
 typedef struct {

@@ -132,9 +132,9 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
       free_plan(p);
       return fail(NNEF_E_ARG, "eps must be a positive finite number");
     }
-    if (p->opt.prec != NNEF_FP32) {
+    if (p->opt.prec != NNEF_FP32 && p->opt.prec != NNEF_BF16 && p->opt.prec != NNEF_FP16) {
       free_plan(p);
-      return fail(NNEF_E_ARG, "only NNEF_FP32 contractions are available in this build");
+      return fail(NNEF_E_ARG, "prec must be NNEF_FP32, NNEF_BF16 or NNEF_FP16");
     }
   }
   std::string err;
@@ -258,7 +258,9 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
       free_plan(p);
       return st;
     }
-    p->description += describe_block(m, bp) + "\n";
+    const bool lp = bp.KP == 32 && bp.qstep == 32 && p->opt.prec != NNEF_FP32;
+    p->description += describe_block(m, bp) +
+                      (lp ? (p->opt.prec == NNEF_BF16 ? " contract=bf16" : " contract=fp16") : " contract=fp32") + "\n";
   }
   if (hipDeviceSynchronize() != hipSuccess) {
     free_plan(p);
@@ -362,6 +364,7 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.ab_inv = ab != 0 ? (float)(1.0 / ab) : 0.f;
   a.apb_inv = apb != 0 ? (float)(1.0 / apb) : 0.f;
   a.lk = p->ls.lk;
+  a.prec = (bp.KP == 32 && bp.qstep == 32) ? p->opt.prec : 0;
   a.full = (bp.K == bp.KP && bp.nqi % bp.qstep == 0 && bp.nP % bp.rows == 0 && bp.in_stride == 1 &&
             bp.pieces[bp.inner].ld == bp.KP) ? 1 : 0;
   return a;

@@ -22,7 +22,36 @@ __device__ __forceinline__ f16v mfma32(float a, float b, const f16v& c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-template <int WK, bool VECQ, int MODE, bool FULL>
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// Reduced-precision contraction operands: MFMA m (0, 1) of the K = 16 form
+// takes this lane's accumulator rows v = 8m .. 8m+7 as its eight K slots; the
+// A and B operands use the same permutation of q, so the sum is unchanged.
+template <int PREC>
+__device__ __forceinline__ f16v mfma_lp(const float* av, const float* bv, const f16v& c) {
+  if constexpr (PREC == 1) {
+    bf16x8 x, y;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      x[j] = (__bf16)av[j];
+      y[j] = (__bf16)bv[j];
+    }
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
+  } else {
+    f16x8 x, y;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      x[j] = (_Float16)av[j];
+      y[j] = (_Float16)bv[j];
+    }
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
+  }
+}
+
+// PREC: input precision of the numerator/denominator contractions
+// (0 = FP32, 1 = BF16, 2 = FP16); the reconstruction is always FP32.
+template <int WK, bool VECQ, int MODE, bool FULL, int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_x32(
     FusedArgs a) {
   constexpr int KP = 32, ROWS = 32, RST = KP + 4;
@@ -225,11 +254,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       float rb[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) rb[v] = cl.Rb[v] * ul;
+      if constexpr (PREC == 0) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) accN = mfma32(rb[v], wa[v], accN);
-      if (!a.no_d) {
+        for (int v = 0; v < 16; ++v) accN = mfma32(rb[v], wa[v], accN);
+        if (!a.no_d) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) accD = mfma32(rb[v], wb[v], accD);
+          for (int v = 0; v < 16; ++v) accD = mfma32(rb[v], wb[v], accD);
+        }
+      } else {
+        float wav[16], wbv[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          wav[v] = wa[v];
+          wbv[v] = wb[v];
+        }
+        accN = mfma_lp<PREC>(rb, wav, accN);
+        accN = mfma_lp<PREC>(rb + 8, wav + 8, accN);
+        if (!a.no_d) {
+          accD = mfma_lp<PREC>(rb, wbv, accD);
+          accD = mfma_lp<PREC>(rb + 8, wbv + 8, accD);
+        }
       }
     }
   };
@@ -394,13 +438,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+template <int WK, bool VECQ, int MODE, int PREC>
+int launch_x32_p(const FusedArgs& a, hipStream_t s) {
+  if (a.full)
+    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+  return (int)hipGetLastError();
+}
+
 template <int WK, bool VECQ, int MODE>
 int launch_x32_t(const FusedArgs& a, hipStream_t s) {
-  if (a.full)
-    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, true>), dim3(a.n_wg), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, false>), dim3(a.n_wg), dim3(256), 0, s, a);
-  return (int)hipGetLastError();
+  if (MODE == 2 || a.prec == 0) return launch_x32_p<WK, VECQ, MODE, 0>(a, s);  // the loss pass has no contraction
+  if (a.prec == 1) return launch_x32_p<WK, VECQ, MODE, 1>(a, s);
+  return launch_x32_p<WK, VECQ, MODE, 2>(a, s);
 }
 
 template <int WK>

@@ -83,6 +83,7 @@ struct FusedArgs {
   float ab_inv, apb_inv;       // 1/(alpha*beta), 1/(alpha+beta)
   int lk;                      // LossKind (generic weights only)
   int full;                    // no ragged edges: K = KP, nqi % 16 = 0, nP % rows = 0
+  int prec;                    // contraction inputs: 0 FP32, 1 BF16, 2 FP16 (width 32)
 };
 
 // Reduce the partials of a fused pass and apply the update (or store N_L/D_L).

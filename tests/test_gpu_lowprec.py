@@ -1,0 +1,65 @@
+"""Reduced-precision contractions (BF16 / FP16 inputs, FP32 accumulation) vs
+the FP64 oracle: one sweep from an identical state matches at relative 1e-2
+per factor; the reconstruction and loss stay FP32, so the loss trace still
+matches the oracle at 1e-5."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2602_02759_amd import datagen
+
+from _gpu_util import EPS, assert_step_parity, clamp_init, gpu_sweeps, oracle_sweep
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(p, prec):
+    from paper_2602_02759_amd.nnef import Plan
+    return Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, eps=EPS, prec=prec)
+
+
+CASES = {
+    "cp3_full_euc": lambda: datagen.cp3(1.0, 1.0),
+    "cp3_full_ab": lambda: datagen.cp3(0.5, 1.0),
+    "cp3_small_kl": lambda: datagen.cp3(1.0, 0.0, sizes=dict(i=48, j=40, k=36), R=32, seed=25),
+    "cp3_ragged_euc": lambda: datagen.cp3(1.0, 1.0, sizes=dict(i=37, j=45, k=29), R=27, seed=26),
+}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_lowprec_step(prec, name):
+    p = CASES[name]()
+    plan = _plan(p, prec)
+    desc = plan.describe()
+    print(desc, flush=True)
+    assert f"contract={prec}" in desc
+    s0 = clamp_init(p)
+    g1 = gpu_sweeps(plan, p, s0, 1)
+    worst = assert_step_parity(g1, oracle_sweep(p, s0), 1e-2, f"{name} {prec}")
+    print(f"{name} {prec}: worst rel error {worst:.2e}")
+    g2 = gpu_sweeps(plan, p, g1, 1)
+    assert_step_parity(g2, oracle_sweep(p, g1), 1e-2, f"{name} {prec} step 2")
+
+
+def test_bf16_loss_trace_stays_fp32_accurate():
+    p = CASES["cp3_small_kl"]()
+    plan = _plan(p, "bf16")
+    s0 = clamp_init(p)
+    g, tr = gpu_sweeps(plan, p, s0, 5, trace=True)
+    ref = O.loss(p.model_str, [s.astype(np.float64) for s in s0], p.Y, p.M, p.alpha, p.beta)
+    assert abs(tr[0] - ref) <= 1e-5 * ref
+    assert np.all(np.diff(tr) <= 1e-6 * tr[:-1]), tr
+
+
+def test_bf16_trajectory_final_loss():
+    """50 sweeps with BF16 contractions reach the FP64 oracle's 50-sweep loss
+    within 1e-3 relative (both losses evaluated by the oracle)."""
+    p = CASES["cp3_small_kl"]()
+    plan = _plan(p, "bf16")
+    g = gpu_sweeps(plan, p, clamp_init(p), 50)
+    ref = O.fit(p.model_str, p.init, p.Y, p.M, p.alpha, p.beta, EPS, n_sweeps=50)
+    lg = O.loss(p.model_str, [x.astype(np.float64) for x in g], p.Y, p.M, p.alpha, p.beta)
+    lr = O.loss(p.model_str, ref, p.Y, p.M, p.alpha, p.beta)
+    print(f"bf16 50-sweep loss {lg:.8e} oracle {lr:.8e} rel {(lg - lr) / lr:.2e}")
+    assert abs(lg - lr) <= 1e-3 * lr
