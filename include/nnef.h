@@ -152,6 +152,88 @@ nnef_status nnef_loss_device(nnef_plan_t plan, const float* Y, const uint8_t* ma
 nnef_status nnef_plan_set_timing(nnef_plan_t plan, int enable);
 nnef_status nnef_plan_timing(nnef_plan_t plan, int* n_passes, double* total_ms);
 
+/* ------------------------------------------------------------------------
+ * Learned extrapolation of the iterates.
+ *
+ * The paper has no learned component; this is the library's own addition on
+ * top of Algorithm 1.  A small network (8 -> 128 -> 128 -> 1, ReLU, softplus
+ * output s >= 0) reads eight features of every factor element's recent
+ * multiplicative-update iterates theta_t, theta_{t-1}, theta_{t-2}:
+ *   d1 = log(theta_t / theta_{t-1}), d2 = log(theta_{t-1} / theta_{t-2}),
+ *   sigma = root mean square of d1 over the element's factor,
+ *   x = [d1/sigma, d2/sigma, log10(sigma)/8, (log theta_t - log eps)/|log eps|,
+ *        log10(max(rel_dec, 1e-30))/8, gamma, log2(K)/8, 1]
+ * (rel_dec = (loss_{t-1} - loss_t)/loss_t; gamma = the update exponent, 1 for
+ * the exponential update; K = the factor's last-axis size), and proposes
+ * theta' = max(eps, theta_t exp(s d1)), positive by construction.
+ *
+ * Parameters are float32 in one flat vector of nnef_mlp_num_params() values:
+ * W1 [8][128] (input-major), b1 [128], W2 [128][128] (W2[i][j] joins unit i
+ * of layer 1 to unit j of layer 2), b2 [128], w3 [128], b3 [1].  The 128 x 128
+ * layer runs on BF16 MFMA with float32 accumulation (forward and backward);
+ * everything else is float32.
+ * ------------------------------------------------------------------------ */
+typedef struct nnef_mlp_s* nnef_mlp_t;
+
+int nnef_mlp_num_params(void);
+
+/* Create a network from initial parameters (device, float32, layout above;
+ * copied, the caller keeps ownership).  Adam moments start at zero.  Syncs
+ * the device. */
+nnef_status nnef_mlp_create(const float* d_init_params, nnef_mlp_t* out);
+void nnef_mlp_destroy(nnef_mlp_t mlp);
+
+/* Copy the current float32 parameters to d_out (device). */
+nnef_status nnef_mlp_params(nnef_mlp_t mlp, float* d_out, void* stream);
+
+/* s[r] = softplus(network(X[r])) for n_rows rows X [n_rows][8] (device). */
+nnef_status nnef_mlp_forward(nnef_mlp_t mlp, const float* X, int64_t n_rows, float* s_out,
+                             void* stream);
+
+/*
+ * Training loss over n_rows rows: mean over rows of (s X[r][0] - tau[r])^2,
+ * where rows are X[idx[r]], tau[idx[r]] (idx: device int32, or NULL for
+ * r = 0..n_rows-1).  nnef_mlp_gradient writes the gradient (float32, the
+ * parameter layout) to d_grad and the loss to *d_loss (device, may be NULL);
+ * nnef_mlp_train_step instead applies one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected; Kingma and Ba 2015) with learning rate lr.  The
+ * gradient is summed over workgroups in a fixed order (deterministic).
+ */
+nnef_status nnef_mlp_gradient(nnef_mlp_t mlp, const float* X, const float* tau, const int32_t* idx,
+                              int64_t n_rows, float* d_grad, double* d_loss, void* stream);
+nnef_status nnef_mlp_train_step(nnef_mlp_t mlp, const float* X, const float* tau,
+                                const int32_t* idx, int64_t n_rows, double lr, double* d_loss,
+                                void* stream);
+
+/*
+ * Training rows from a multiplicative-update trajectory of `plan`'s model:
+ * for every factor element (factors concatenated in operand order), the eight
+ * features above into X [numel_total][8], and, when th_target (theta_{t+h})
+ * is given, the target tau = clip(log(theta_{t+h}/theta_t)/sigma, -64, 64).
+ * All arrays are host arrays of L device pointers / device buffers.
+ * Returns NNEF_E_UNSUPPORTED for models with more than 8 factors.
+ */
+nnef_status nnef_learned_rows(nnef_plan_t plan, const float* const* th_t,
+                              const float* const* th_tm1, const float* const* th_tm2,
+                              const float* const* th_target, double rel_dec, float* X, float* tau,
+                              void* stream);
+
+/*
+ * nnef_step - with proposals: n_sweeps sweeps of Algorithm 1; after every
+ * sweep t that is a multiple of propose_every (>= 3) the network proposes
+ * theta' from theta_t, theta_{t-1}, theta_{t-2}; the proposal replaces the
+ * factors only if its loss (float32 terms, float64 sum, computed on the GPU)
+ * is strictly lower than the loss of theta_t.  Otherwise the iterate is kept,
+ * so the loss never increases.  loss_trace as in nnef_step (device, may be
+ * NULL); *d_n_accepted (device int, may be NULL) is incremented per accepted
+ * proposal.  Enqueue only.  Uses plan-owned buffers: calls on one plan must not
+ * overlap.
+ */
+nnef_status nnef_step_learned(nnef_plan_t plan, nnef_mlp_t mlp, const float* Y,
+                              const uint8_t* mask, float* const* factors, int n_sweeps,
+                              int propose_every, double* loss_trace, int* d_n_accepted,
+                              void* stream);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* nnef_last_error(void);
 

@@ -21,7 +21,9 @@ follow, written out plainly in float64:
 * Proposal: log theta' = log theta_t + s d1, theta' = max(eps, exp(.)), so the
   proposal is positive by construction.
 * Training rows: target tau = (log theta_{t+h} - log theta_t) / sigma for a
-  horizon of h sweeps; row loss (s x0 - tau)^2, averaged over the batch.
+  horizon of h sweeps, clipped to [-64, 64] (elements falling to the eps
+  floor would otherwise dominate); row loss (s x0 - tau)^2, averaged over the
+  batch.
 * Adam (Kingma and Ba, 2015) with bias correction on float32 master weights.
 
 Parameter vector layout (float64 here, float32 on the GPU), in this order:
@@ -136,9 +138,9 @@ def features(th_t, th_tm1, th_tm2, rel_dec, gamma, eps):
 
 
 def targets(th_t, th_th, sigma):
-    """Training targets tau = (log theta_{t+h} - log theta_t) / sigma."""
-    return ((np.log(np.asarray(th_th, dtype=np.float64)) - np.log(np.asarray(th_t, dtype=np.float64)))
-            .ravel() / sigma)
+    """Training targets tau = clip((log theta_{t+h} - log theta_t) / sigma, -64, 64)."""
+    return np.clip((np.log(np.asarray(th_th, dtype=np.float64))
+                    - np.log(np.asarray(th_t, dtype=np.float64))).ravel() / sigma, -64.0, 64.0)
 
 
 def propose(theta, th_t, th_tm1, th_tm2, rel_dec, gamma, eps):

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnnef.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "fused16.hip", "fused32.hip", "fused64.hip", "planner.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "learned.hip", "fused16.hip", "fused32.hip", "fused64.hip", "planner.cpp", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel

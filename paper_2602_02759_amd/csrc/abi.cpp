@@ -49,6 +49,9 @@ struct nnef_plan_s {
   int64_t n_data = 0;
   int max_wg = 0;
   std::vector<int64_t> numel;
+  int64_t numel_total = 0;
+  float* learn_buf = nullptr;      // 3 x numel_total: theta_{t-1}, theta_{t-2}, proposal
+  double* learn_small = nullptr;   // sigma per factor, then losses
   std::string description;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -85,6 +88,8 @@ static void free_plan(nnef_plan_s* p) {
   if (p->loss_tmp) (void)hipFree(p->loss_tmp);
   if (p->dcol) (void)hipFree(p->dcol);
   if (p->ypack) (void)hipFree(p->ypack);
+  if (p->learn_buf) (void)hipFree(p->learn_buf);
+  if (p->learn_small) (void)hipFree(p->learn_small);
   delete p;
 }
 
@@ -240,6 +245,14 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
     free_plan(p);
     return fail(NNEF_E_NOMEM, "partial-sum allocation failed");
   }
+  for (auto n : p->numel) p->numel_total += n;
+  if ((int)m.ops.size() <= kMaxLearnFactors) {
+    if (hipMalloc((void**)&p->learn_buf, (size_t)(3 * p->numel_total) * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&p->learn_small, (kMaxLearnFactors + 8) * sizeof(double)) != hipSuccess) {
+      free_plan(p);
+      return fail(NNEF_E_NOMEM, "extrapolation buffer allocation failed");
+    }
+  }
   for (auto& bp : p->blocks) {
     nnef_status st = upload_table(p, offsets_table(m, bp.P), &bp.d_poff);
     if (st == NNEF_OK) st = upload_table(p, offsets_table(m, bp.qo), &bp.d_qoyoff);
@@ -377,15 +390,107 @@ static int run_side_prep(const nnef_plan_s* p, const BlockPlan& bp, const float*
   return e;
 }
 
-nnef_status nnef_step(nnef_plan_t p, const float* Y, const uint8_t* M, float* const* factors,
-                      int n_sweeps, double* loss_trace, void* stream) {
+// One sweep of Algorithm 1 over packed data; loss_slot (device, may be null)
+// receives the loss at the start of the sweep.
+static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float* const* factors,
+                             double* loss_slot, hipStream_t s) {
+  const int L = (int)p->m.ops.size();
+  const float* const* cf = factors;
+  for (int l = 0; l < L; ++l) {
+    const BlockPlan& bp = p->blocks[l];
+    int e = run_side_prep(p, bp, cf, s);
+    if (e) return hip_fail(e, "side-operand contraction launch");
+    FusedArgs fa = fused_args(p, bp, Yd, masked, cf);
+    const bool want_loss = loss_slot && l == 0;
+    fa.loss_part = want_loss ? p->loss_part : nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (p->timing) {
+      if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess ||
+          hipEventRecord(ev0, s) != hipSuccess)
+        return fail(NNEF_E_DEVICE, "timing event set-up failed");
+    }
+    e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, want_loss ? 1 : 0, s);
+    if (e) return hip_fail(e, "fused pass launch");
+    if (p->timing) {
+      if (hipEventRecord(ev1, s) != hipSuccess) return fail(NNEF_E_DEVICE, "timing event record failed");
+      p->events.emplace_back(ev0, ev1);
+    }
+    UpdateArgs ua;
+    std::memset(&ua, 0, sizeof(ua));
+    ua.partN = p->partN;
+    ua.partD = p->partD;
+    ua.n_chunks = bp.n_chunks;
+    ua.nP = (int)bp.nP;
+    ua.K = bp.K;
+    ua.KP = bp.KP;
+    ua.no_d = fa.no_d;
+    ua.npieces = (int)bp.pieces.size();
+    for (int i = 0; i < ua.npieces; ++i) {
+      ua.piece[i] = piece_ptr(p, bp.pieces[i], cf);
+      ua.ldpiece[i] = bp.pieces[i].ld;
+      ua.nrows[i] = bp.pieces[i].nrows;
+    }
+    ua.theta = bp.L_direct ? factors[l] : nullptr;
+    ua.ldT = bp.ldL;
+    ua.NL = bp.L_direct ? nullptr : p->ws[bp.NL_buf];
+    ua.DL = bp.L_direct ? nullptr : p->ws[bp.DL_buf];
+    ua.upd = p->ls.upd;
+    ua.gamma = (float)p->ls.gamma;
+    ua.eps = (float)p->opt.eps;
+    if (want_loss) {
+      ua.loss_part = p->loss_part;
+      ua.n_loss_part = bp.n_wg;
+      ua.loss_out = loss_slot;
+    }
+    e = launch_update(ua, p->dcol, s);
+    if (e) return hip_fail(e, "update launch");
+    if (!bp.L_direct) {
+      e = run_program(p, bp, bp.chainN, cf, s);
+      if (!e) e = run_program(p, bp, bp.chainD, cf, s);
+      if (e) return hip_fail(e, "chain-back contraction launch");
+      ApplyArgs aa;
+      aa.theta = factors[l];
+      aa.N = p->ws[bp.Nl_buf];
+      aa.D = p->ws[bp.Dl_buf];
+      aa.n = p->numel[l];
+      aa.upd = p->ls.upd;
+      aa.gamma = (float)p->ls.gamma;
+      aa.eps = (float)p->opt.eps;
+      e = launch_apply(aa, s);
+      if (e) return hip_fail(e, "update launch");
+    }
+  }
+  return NNEF_OK;
+}
+
+// The loss of the given factors over packed data, into d_loss (device).
+static nnef_status run_loss(nnef_plan_s* p, const float* Yd, bool masked, const float* const* factors,
+                            double* d_loss, hipStream_t s) {
+  const BlockPlan& bp = p->blocks[0];
+  int e = run_side_prep(p, bp, factors, s);
+  if (e) return hip_fail(e, "side-operand contraction launch");
+  FusedArgs fa = fused_args(p, bp, Yd, masked, factors);
+  fa.loss_part = p->loss_part;
+  e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, 2, s);
+  if (e) return hip_fail(e, "loss pass launch");
+  e = launch_loss_final(p->loss_part, bp.n_wg, d_loss, s);
+  if (e) return hip_fail(e, "loss reduction launch");
+  return NNEF_OK;
+}
+
+static nnef_status check_step_args(nnef_plan_s* p, const float* Y, const void* factors, int n_sweeps) {
   if (!p || !Y || !factors) return fail(NNEF_E_ARG, "plan, Y and factors must not be NULL");
   if (n_sweeps < 0) return fail(NNEF_E_ARG, "n_sweeps must be >= 0");
-  const int L = (int)p->m.ops.size();
-  for (int l = 0; l < L; ++l)
-    if (!factors[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
+  for (int l = 0; l < (int)p->m.ops.size(); ++l)
+    if (!((float* const*)factors)[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
+  return NNEF_OK;
+}
+
+nnef_status nnef_step(nnef_plan_t p, const float* Y, const uint8_t* M, float* const* factors,
+                      int n_sweeps, double* loss_trace, void* stream) {
+  nnef_status st = check_step_args(p, Y, factors, n_sweeps);
+  if (st != NNEF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const float* const* cf = factors;
   const float* Yd = Y;
   if (M && n_sweeps > 0) {
     const int e = launch_pack(Y, M, p->ypack, p->n_data, s);
@@ -393,70 +498,8 @@ nnef_status nnef_step(nnef_plan_t p, const float* Y, const uint8_t* M, float* co
     Yd = p->ypack;
   }
   for (int sw = 0; sw < n_sweeps; ++sw) {
-    for (int l = 0; l < L; ++l) {
-      const BlockPlan& bp = p->blocks[l];
-      int e = run_side_prep(p, bp, cf, s);
-      if (e) return hip_fail(e, "side-operand contraction launch");
-      FusedArgs fa = fused_args(p, bp, Yd, M != nullptr, cf);
-      const bool want_loss = loss_trace && l == 0;
-      fa.loss_part = want_loss ? p->loss_part : nullptr;
-      hipEvent_t ev0 = nullptr, ev1 = nullptr;
-      if (p->timing) {
-        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess ||
-            hipEventRecord(ev0, s) != hipSuccess)
-          return fail(NNEF_E_DEVICE, "timing event set-up failed");
-      }
-      e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, want_loss ? 1 : 0, s);
-      if (e) return hip_fail(e, "fused pass launch");
-      if (p->timing) {
-        if (hipEventRecord(ev1, s) != hipSuccess) return fail(NNEF_E_DEVICE, "timing event record failed");
-        p->events.emplace_back(ev0, ev1);
-      }
-      UpdateArgs ua;
-      std::memset(&ua, 0, sizeof(ua));
-      ua.partN = p->partN;
-      ua.partD = p->partD;
-      ua.n_chunks = bp.n_chunks;
-      ua.nP = (int)bp.nP;
-      ua.K = bp.K;
-      ua.KP = bp.KP;
-      ua.no_d = fa.no_d;
-      ua.npieces = (int)bp.pieces.size();
-      for (int i = 0; i < ua.npieces; ++i) {
-        ua.piece[i] = piece_ptr(p, bp.pieces[i], cf);
-        ua.ldpiece[i] = bp.pieces[i].ld;
-        ua.nrows[i] = bp.pieces[i].nrows;
-      }
-      ua.theta = bp.L_direct ? factors[l] : nullptr;
-      ua.ldT = bp.ldL;
-      ua.NL = bp.L_direct ? nullptr : p->ws[bp.NL_buf];
-      ua.DL = bp.L_direct ? nullptr : p->ws[bp.DL_buf];
-      ua.upd = p->ls.upd;
-      ua.gamma = (float)p->ls.gamma;
-      ua.eps = (float)p->opt.eps;
-      if (want_loss) {
-        ua.loss_part = p->loss_part;
-        ua.n_loss_part = bp.n_wg;
-        ua.loss_out = loss_trace + sw;
-      }
-      e = launch_update(ua, p->dcol, s);
-      if (e) return hip_fail(e, "update launch");
-      if (!bp.L_direct) {
-        e = run_program(p, bp, bp.chainN, cf, s);
-        if (!e) e = run_program(p, bp, bp.chainD, cf, s);
-        if (e) return hip_fail(e, "chain-back contraction launch");
-        ApplyArgs aa;
-        aa.theta = factors[l];
-        aa.N = p->ws[bp.Nl_buf];
-        aa.D = p->ws[bp.Dl_buf];
-        aa.n = p->numel[l];
-        aa.upd = p->ls.upd;
-        aa.gamma = (float)p->ls.gamma;
-        aa.eps = (float)p->opt.eps;
-        e = launch_apply(aa, s);
-        if (e) return hip_fail(e, "update launch");
-      }
-    }
+    st = run_sweep(p, Yd, M != nullptr, factors, loss_trace ? loss_trace + sw : nullptr, s);
+    if (st != NNEF_OK) return st;
   }
   return NNEF_OK;
 }
@@ -490,23 +533,13 @@ nnef_status nnef_loss_device(nnef_plan_t p, const float* Y, const uint8_t* M,
   for (int l = 0; l < (int)p->m.ops.size(); ++l)
     if (!factors[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
-  const BlockPlan& bp = p->blocks[0];
-  int e = 0;
   const float* Yd = Y;
   if (M) {
-    e = launch_pack(Y, M, p->ypack, p->n_data, s);
+    const int e = launch_pack(Y, M, p->ypack, p->n_data, s);
     if (e) return hip_fail(e, "data packing launch");
     Yd = p->ypack;
   }
-  e = run_side_prep(p, bp, factors, s);
-  if (e) return hip_fail(e, "side-operand contraction launch");
-  FusedArgs fa = fused_args(p, bp, Yd, M != nullptr, factors);
-  fa.loss_part = p->loss_part;
-  e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, 2, s);
-  if (e) return hip_fail(e, "loss pass launch");
-  e = launch_loss_final(p->loss_part, bp.n_wg, d_loss, s);
-  if (e) return hip_fail(e, "loss reduction launch");
-  return NNEF_OK;
+  return run_loss(p, Yd, M != nullptr, factors, d_loss, s);
 }
 
 nnef_status nnef_loss(nnef_plan_t p, const float* Y, const uint8_t* M, const float* const* factors,
@@ -518,6 +551,230 @@ nnef_status nnef_loss(nnef_plan_t p, const float* Y, const uint8_t* M, const flo
   hipError_t e = hipMemcpyAsync(loss_out, p->loss_tmp, sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "loss copy");
+  return NNEF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned extrapolation
+struct nnef_mlp_s {
+  float* params = nullptr;   // FP32 master parameters
+  float* m = nullptr;        // Adam moments
+  float* v = nullptr;
+  float* gpart = nullptr;    // [256, kMlpParams] gradient partials
+  double* lpart = nullptr;   // [256]
+  int64_t t = 0;             // Adam steps taken
+};
+
+static void free_mlp(nnef_mlp_s* q) {
+  if (!q) return;
+  for (void* b : {(void*)q->params, (void*)q->m, (void*)q->v, (void*)q->gpart, (void*)q->lpart})
+    if (b) (void)hipFree(b);
+  delete q;
+}
+
+int nnef_mlp_num_params(void) { return kMlpParams; }
+
+nnef_status nnef_mlp_create(const float* d_init, nnef_mlp_t* out) {
+  if (!d_init || !out) return fail(NNEF_E_ARG, "d_init and out must not be NULL");
+  *out = nullptr;
+  nnef_mlp_s* q = new nnef_mlp_s();
+  const size_t pb = kMlpParams * sizeof(float);
+  if (hipMalloc((void**)&q->params, pb) != hipSuccess || hipMalloc((void**)&q->m, pb) != hipSuccess ||
+      hipMalloc((void**)&q->v, pb) != hipSuccess ||
+      hipMalloc((void**)&q->gpart, 256 * pb) != hipSuccess ||
+      hipMalloc((void**)&q->lpart, 256 * sizeof(double)) != hipSuccess) {
+    free_mlp(q);
+    return fail(NNEF_E_NOMEM, "MLP allocation failed");
+  }
+  if (hipMemcpy(q->params, d_init, pb, hipMemcpyDeviceToDevice) != hipSuccess ||
+      hipMemset(q->m, 0, pb) != hipSuccess || hipMemset(q->v, 0, pb) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    free_mlp(q);
+    return fail(NNEF_E_DEVICE, "MLP initialisation failed");
+  }
+  *out = q;
+  return NNEF_OK;
+}
+
+void nnef_mlp_destroy(nnef_mlp_t q) { free_mlp(q); }
+
+nnef_status nnef_mlp_params(nnef_mlp_t q, float* d_out, void* stream) {
+  if (!q || !d_out) return fail(NNEF_E_ARG, "NULL argument");
+  const hipError_t e = hipMemcpyAsync(d_out, q->params, kMlpParams * sizeof(float),
+                                      hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  return e == hipSuccess ? NNEF_OK : hip_fail(e, "parameter copy");
+}
+
+nnef_status nnef_mlp_forward(nnef_mlp_t q, const float* X, int64_t n_rows, float* s_out, void* stream) {
+  if (!q || (n_rows > 0 && (!X || !s_out)) || n_rows < 0) return fail(NNEF_E_ARG, "bad argument");
+  if (n_rows == 0) return NNEF_OK;
+  MlpArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.params = q->params;
+  a.n_rows = n_rows;
+  a.X = X;
+  a.s_out = s_out;
+  const int e = launch_mlp(a, 0, mlp_grid(n_rows), stream);
+  return e ? hip_fail(e, "MLP forward launch") : NNEF_OK;
+}
+
+static nnef_status mlp_grad(nnef_mlp_s* q, const float* X, const float* tau, const int32_t* idx,
+                            int64_t n_rows, float* grad_out, double* loss_out, double lr, int adam,
+                            void* stream) {
+  if (!q || !X || !tau || n_rows <= 0) return fail(NNEF_E_ARG, "bad argument");
+  if (n_rows >= (int64_t(1) << 31)) return fail(NNEF_E_SHAPE, "too many rows");
+  MlpArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.params = q->params;
+  a.n_rows = n_rows;
+  a.X = X;
+  a.tau = tau;
+  a.idx = idx;
+  a.inv_n = (float)(1.0 / (double)n_rows);
+  a.gpart = q->gpart;
+  a.lpart = q->lpart;
+  const int grid = mlp_grid(n_rows);
+  int e = launch_mlp(a, 1, grid, stream);
+  if (e) return hip_fail(e, "MLP gradient launch");
+  const float b1 = 0.9f, b2 = 0.999f;
+  float bc1 = 1.f, bc2 = 1.f;
+  if (adam) {
+    q->t += 1;
+    bc1 = (float)(1.0 - std::pow(0.9, (double)q->t));
+    bc2 = (float)(1.0 - std::pow(0.999, (double)q->t));
+  }
+  e = launch_mlp_reduce(q->gpart, q->lpart, grid, a.inv_n, grad_out, loss_out, q->params, q->m, q->v,
+                        (float)lr, b1, b2, 1e-8f, bc1, bc2, adam, stream);
+  return e ? hip_fail(e, "MLP reduction launch") : NNEF_OK;
+}
+
+nnef_status nnef_mlp_gradient(nnef_mlp_t q, const float* X, const float* tau, const int32_t* idx,
+                              int64_t n_rows, float* d_grad, double* d_loss, void* stream) {
+  if (!d_grad) return fail(NNEF_E_ARG, "d_grad must not be NULL");
+  return mlp_grad(q, X, tau, idx, n_rows, d_grad, d_loss, 0.0, 0, stream);
+}
+
+nnef_status nnef_mlp_train_step(nnef_mlp_t q, const float* X, const float* tau, const int32_t* idx,
+                                int64_t n_rows, double lr, double* d_loss, void* stream) {
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(NNEF_E_ARG, "lr must be positive and finite");
+  return mlp_grad(q, X, tau, idx, n_rows, nullptr, d_loss, lr, 1, stream);
+}
+
+// Feature arguments for the plan's factors.
+static nnef_status feat_args(nnef_plan_s* p, const float* const* th, const float* const* tm1,
+                             const float* const* tm2, FeatArgs& f) {
+  const int L = (int)p->m.ops.size();
+  if (!p->learn_buf) return fail(NNEF_E_UNSUPPORTED, "learned extrapolation supports at most 8 factors");
+  std::memset(&f, 0, sizeof(f));
+  f.n_fac = L;
+  f.off[0] = 0;
+  for (int k = 0; k < L; ++k) {
+    f.off[k + 1] = f.off[k] + p->numel[k];
+    f.th[k] = th[k];
+    f.tm1[k] = tm1[k];
+    f.tm2[k] = tm2[k];
+    const std::string& sub = p->m.ops[k];
+    const int64_t K = sub.empty() ? 1 : p->m.size[(unsigned char)sub.back()];
+    f.logK8[k] = (float)(std::log2((double)K) / 8.0);
+  }
+  f.sigma = p->learn_small;
+  f.gamma = (float)(p->ls.upd == UP_EXP ? 1.0 : p->ls.gamma);
+  f.eps = (float)p->opt.eps;
+  f.log_eps = (float)std::log(p->opt.eps);
+  f.inv_abs_log_eps = (float)(1.0 / std::fabs(std::log(p->opt.eps)));
+  return NNEF_OK;
+}
+
+nnef_status nnef_learned_rows(nnef_plan_t p, const float* const* th_t, const float* const* th_tm1,
+                              const float* const* th_tm2, const float* const* th_target, double rel_dec,
+                              float* X, float* tau, void* stream) {
+  if (!p || !th_t || !th_tm1 || !th_tm2 || !X) return fail(NNEF_E_ARG, "NULL argument");
+  if ((th_target == nullptr) != (tau == nullptr))
+    return fail(NNEF_E_ARG, "th_target and tau must both be given or both be NULL");
+  FeatArgs f;
+  nnef_status st = feat_args(p, th_t, th_tm1, th_tm2, f);
+  if (st != NNEF_OK) return st;
+  f.rel_dec = rel_dec;
+  for (int k = 0; k < f.n_fac; ++k) {
+    if (!th_t[k] || !th_tm1[k] || !th_tm2[k] || (th_target && !th_target[k]))
+      return fail(NNEF_E_ARG, "factor pointer is NULL");
+    f.tth[k] = th_target ? th_target[k] : nullptr;
+  }
+  int e = launch_sigma(f, stream);
+  if (!e) e = launch_rows(f, X, tau, stream);
+  return e ? hip_fail(e, "feature launch") : NNEF_OK;
+}
+
+nnef_status nnef_step_learned(nnef_plan_t p, nnef_mlp_t q, const float* Y, const uint8_t* M,
+                              float* const* factors, int n_sweeps, int propose_every,
+                              double* loss_trace, int* d_n_accepted, void* stream) {
+  nnef_status st = check_step_args(p, Y, factors, n_sweeps);
+  if (st != NNEF_OK) return st;
+  if (!q) return fail(NNEF_E_ARG, "mlp must not be NULL");
+  if (propose_every < 3) return fail(NNEF_E_ARG, "propose_every must be >= 3");
+  if (!p->learn_buf) return fail(NNEF_E_UNSUPPORTED, "learned extrapolation supports at most 8 factors");
+  hipStream_t s = (hipStream_t)stream;
+  const int L = (int)p->m.ops.size();
+  const float* Yd = Y;
+  if (M && n_sweeps > 0) {
+    const int e = launch_pack(Y, M, p->ypack, p->n_data, s);
+    if (e) return hip_fail(e, "data packing launch");
+    Yd = p->ypack;
+  }
+  // plan-owned buffers: theta_{t-1}, theta_{t-2}, the proposal
+  float* h1[kMaxLearnFactors];
+  float* h2[kMaxLearnFactors];
+  float* cand[kMaxLearnFactors];
+  int64_t o = 0;
+  for (int k = 0; k < L; ++k) {
+    h1[k] = p->learn_buf + o;
+    h2[k] = p->learn_buf + p->numel_total + o;
+    cand[k] = p->learn_buf + 2 * p->numel_total + o;
+    o += p->numel[k];
+  }
+  double* loss_prev_slot = p->learn_small + kMaxLearnFactors;  // used when no trace is given
+  double* loss_cur = p->learn_small + kMaxLearnFactors + 1;
+  double* loss_cand = p->learn_small + kMaxLearnFactors + 2;
+  const int P = propose_every;
+  for (int sw = 1; sw <= n_sweeps; ++sw) {
+    // snapshots: theta_{t-2} before sweep t-1, theta_{t-1} before sweep t (t = proposal sweep)
+    if (sw % P == P - 1 || sw % P == 0) {
+      FeatArgs c;
+      st = feat_args(p, factors, sw % P == 0 ? h1 : h2, factors, c);
+      if (st != NNEF_OK) return st;
+      const int e = launch_copy_factors(c, s);
+      if (e) return hip_fail(e, "snapshot launch");
+    }
+    double* slot = loss_trace ? loss_trace + (sw - 1) : loss_prev_slot;
+    st = run_sweep(p, Yd, M != nullptr, factors, slot, s);
+    if (st != NNEF_OK) return st;
+    if (sw % P != 0) continue;
+    // proposal after sweep t = sw from theta_t (factors), theta_{t-1} (h1), theta_{t-2} (h2)
+    st = run_loss(p, Yd, M != nullptr, factors, loss_cur, s);
+    if (st != NNEF_OK) return st;
+    FeatArgs f;
+    st = feat_args(p, factors, h1, h2, f);
+    if (st != NNEF_OK) return st;
+    f.loss_prev = slot;
+    f.loss_cur = loss_cur;
+    for (int k = 0; k < L; ++k) {
+      f.cand[k] = cand[k];
+      f.dst[k] = factors[k];
+    }
+    int e = launch_sigma(f, s);
+    if (e) return hip_fail(e, "feature launch");
+    MlpArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.params = q->params;
+    a.n_rows = p->numel_total;
+    a.f = f;
+    e = launch_mlp(a, 2, mlp_grid(a.n_rows), s);
+    if (e) return hip_fail(e, "proposal launch");
+    st = run_loss(p, Yd, M != nullptr, cand, loss_cand, s);
+    if (st != NNEF_OK) return st;
+    e = launch_accept(f, loss_cand, loss_cur, d_n_accepted, s);
+    if (e) return hip_fail(e, "accept launch");
+  }
   return NNEF_OK;
 }
 

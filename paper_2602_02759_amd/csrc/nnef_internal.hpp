@@ -136,4 +136,54 @@ int launch_zero(float* p, int64_t n, void* stream);
 // Yp[i] = mask[i] ? Y[i] : -1 (observed data are nonnegative).
 int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream);
 
+// ---- learned extrapolation (a small MLP over per-element trajectory features)
+constexpr int kMlpIn = 8, kMlpWidth = 128;
+constexpr int kMlpOffW1 = 0, kMlpOffB1 = kMlpIn * kMlpWidth, kMlpOffW2 = kMlpOffB1 + kMlpWidth,
+              kMlpOffB2 = kMlpOffW2 + kMlpWidth * kMlpWidth, kMlpOffW3 = kMlpOffB2 + kMlpWidth,
+              kMlpOffB3 = kMlpOffW3 + kMlpWidth, kMlpParams = kMlpOffB3 + 1;
+constexpr int kMaxLearnFactors = 8;
+
+// Per-element features of the factors' recent iterates (theta_t, theta_{t-1},
+// theta_{t-2}); the factors are concatenated in operand order.
+struct FeatArgs {
+  int n_fac;
+  int64_t off[kMaxLearnFactors + 1];
+  const float* th[kMaxLearnFactors];
+  const float* tm1[kMaxLearnFactors];
+  const float* tm2[kMaxLearnFactors];
+  const float* tth[kMaxLearnFactors];   // theta_{t+h} (training targets) or null
+  float* cand[kMaxLearnFactors];        // proposal output
+  float* dst[kMaxLearnFactors];         // accept: factors to overwrite
+  float logK8[kMaxLearnFactors];        // log2(contraction width) / 8
+  const double* sigma;                  // [n_fac]
+  const double* loss_prev;              // loss at t-1 (device) or null: use rel_dec
+  const double* loss_cur;               // loss at t (device)
+  double rel_dec;
+  float gamma, eps, log_eps, inv_abs_log_eps;
+};
+
+struct MlpArgs {
+  const float* params;   // FP32 master parameters [kMlpParams]
+  int64_t n_rows;
+  const float* X;        // rows [n_rows or max idx + 1, 8]
+  const float* tau;      // training targets
+  const int32_t* idx;    // optional row indices into X / tau
+  float* s_out;          // forward: step multipliers
+  float inv_n;           // 1 / n_rows (mean loss)
+  float* gpart;          // gradient partials [grid, kMlpParams]
+  double* lpart;         // loss partials [grid]
+  FeatArgs f;            // proposal mode
+};
+
+int mlp_grid(int64_t n_rows);
+int launch_mlp(const MlpArgs& a, int mode, int grid, void* stream);  // 0 forward, 1 gradient, 2 proposal
+int launch_mlp_reduce(const float* gpart, const double* lpart, int grid, float inv_n, float* grad_out,
+                      double* loss_out, float* params, float* m, float* v, float lr, float b1, float b2,
+                      float eps, float bc1, float bc2, int adam, void* stream);
+int launch_sigma(const FeatArgs& f, void* stream);
+int launch_rows(const FeatArgs& f, float* X, float* tau, void* stream);
+int launch_accept(const FeatArgs& f, const double* loss_cand, const double* loss_cur, int* n_acc,
+                  void* stream);
+int launch_copy_factors(const FeatArgs& f, void* stream);  // tm1[k] <- th[k]
+
 }  // namespace nnef

@@ -57,6 +57,27 @@ EXPORTS = {
     "nnef_plan_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double)]),
     "nnef_last_error": (ctypes.c_char_p, []),
+    "nnef_mlp_num_params": (ctypes.c_int, []),
+    "nnef_mlp_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "nnef_mlp_destroy": (None, [ctypes.c_void_p]),
+    "nnef_mlp_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_mlp_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_learned_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_step_learned": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -171,6 +192,109 @@ def nnef_loss_device(h, Y, M, factors, d_out, stream=None):
                                   _stream(stream)))
 
 
+def nnef_mlp_num_params():
+    return lib().nnef_mlp_num_params()
+
+
+def nnef_mlp_create(init_params):
+    import torch
+    h = ctypes.c_void_p()
+    if init_params.numel() != nnef_mlp_num_params():
+        raise ValueError(f"expected {nnef_mlp_num_params()} parameters, got {init_params.numel()}")
+    _check(lib().nnef_mlp_create(_ptr(init_params, torch.float32, "init_params"), ctypes.byref(h)))
+    return h
+
+
+def nnef_mlp_destroy(h):
+    lib().nnef_mlp_destroy(h)
+
+
+def nnef_mlp_params(h, d_out, stream=None):
+    import torch
+    _check(lib().nnef_mlp_params(h, _ptr(d_out, torch.float32, "d_out"), _stream(stream)))
+
+
+def nnef_mlp_forward(h, X, s_out, stream=None):
+    import torch
+    _check(lib().nnef_mlp_forward(h, _ptr(X, torch.float32, "X"), X.shape[0],
+                                  _ptr(s_out, torch.float32, "s_out"), _stream(stream)))
+
+
+def nnef_mlp_gradient(h, X, tau, idx, n_rows, d_grad, d_loss=None, stream=None):
+    import torch
+    _check(lib().nnef_mlp_gradient(h, _ptr(X, torch.float32, "X"), _ptr(tau, torch.float32, "tau"),
+                                   _ptr(idx, torch.int32, "idx"), int(n_rows),
+                                   _ptr(d_grad, torch.float32, "d_grad"),
+                                   _ptr(d_loss, torch.float64, "d_loss"), _stream(stream)))
+
+
+def nnef_mlp_train_step(h, X, tau, idx, n_rows, lr, d_loss=None, stream=None):
+    import torch
+    _check(lib().nnef_mlp_train_step(h, _ptr(X, torch.float32, "X"), _ptr(tau, torch.float32, "tau"),
+                                     _ptr(idx, torch.int32, "idx"), int(n_rows), float(lr),
+                                     _ptr(d_loss, torch.float64, "d_loss"), _stream(stream)))
+
+
+def nnef_learned_rows(h, th_t, th_tm1, th_tm2, th_target, rel_dec, X, tau=None, stream=None):
+    import torch
+    _check(lib().nnef_learned_rows(h, _factor_array(th_t), _factor_array(th_tm1),
+                                   _factor_array(th_tm2),
+                                   _factor_array(th_target) if th_target is not None else None,
+                                   float(rel_dec), _ptr(X, torch.float32, "X"),
+                                   _ptr(tau, torch.float32, "tau"), _stream(stream)))
+
+
+def nnef_step_learned(h, mlp, Y, M, factors, n_sweeps, propose_every, loss_trace=None,
+                      n_accepted=None, stream=None):
+    import torch
+    _check(lib().nnef_step_learned(h, mlp, _ptr(Y, torch.float32, "Y"), _ptr(M, torch.uint8, "mask"),
+                                   _factor_array(factors), int(n_sweeps), int(propose_every),
+                                   _ptr(loss_trace, torch.float64, "loss_trace"),
+                                   _ptr(n_accepted, torch.int32, "n_accepted"), _stream(stream)))
+
+
+class Mlp:
+    """Owner of an ``nnef_mlp_t`` (the extrapolation network)."""
+
+    def __init__(self, init_params):
+        self.h = nnef_mlp_create(init_params)
+
+    def params(self):
+        import torch
+        out = torch.empty(nnef_mlp_num_params(), dtype=torch.float32, device="cuda")
+        nnef_mlp_params(self.h, out)
+        return out
+
+    def forward(self, X):
+        import torch
+        s = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        nnef_mlp_forward(self.h, X, s)
+        return s
+
+    def gradient(self, X, tau, idx=None):
+        import torch
+        n = idx.numel() if idx is not None else X.shape[0]
+        g = torch.empty(nnef_mlp_num_params(), dtype=torch.float32, device=X.device)
+        l = torch.empty(1, dtype=torch.float64, device=X.device)
+        nnef_mlp_gradient(self.h, X, tau, idx, n, g, l)
+        return g, l
+
+    def train_step(self, X, tau, lr, idx=None, d_loss=None):
+        n = idx.numel() if idx is not None else X.shape[0]
+        nnef_mlp_train_step(self.h, X, tau, idx, n, lr, d_loss)
+
+    def close(self):
+        if self.h:
+            nnef_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """Owner of an ``nnef_plan_t``; the methods call the C entry points."""
 
@@ -199,6 +323,17 @@ class Plan:
     def loss_device(self, Y, M, factors, d_out, stream=None):
         self._check_factors(factors)
         nnef_loss_device(self.h, Y, M, factors, d_out, stream)
+
+    def rows(self, th_t, th_tm1, th_tm2, th_target, rel_dec, X, tau=None):
+        for f in (th_t, th_tm1, th_tm2) + ((th_target,) if th_target is not None else ()):
+            self._check_factors(f)
+        nnef_learned_rows(self.h, th_t, th_tm1, th_tm2, th_target, rel_dec, X, tau)
+
+    def step_learned(self, mlp, Y, M, factors, n_sweeps, propose_every, loss_trace=None,
+                     n_accepted=None, stream=None):
+        self._check_factors(factors)
+        nnef_step_learned(self.h, mlp.h, Y, M, factors, n_sweeps, propose_every, loss_trace,
+                          n_accepted, stream)
 
     def set_timing(self, enable=True):
         nnef_plan_set_timing(self.h, enable)

@@ -1,0 +1,216 @@
+"""Learned extrapolation on the GPU vs the FP64 MLP oracle, through the C ABI.
+
+Tolerances: the 128 x 128 layer runs on BF16 MFMA, so network outputs and
+gradients match the oracle at relative 1e-2; features, targets and the Adam
+arithmetic are FP32 and match at 1e-5.  Accept/reject is exact: a network
+whose proposals are always rejected reproduces plain sweeps bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as Mlp
+from oracle import oracle as O
+from paper_2602_02759_amd import datagen
+
+from _gpu_util import EPS, clamp_init, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed, scale=1.0, s0=1.0):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(Mlp.N_PARAMS)
+    P = Mlp.unpack(th)
+    P["W1"][:] = rng.normal(0, scale * np.sqrt(2 / 8), (8, 128))
+    P["b1"][:] = rng.normal(0, 0.1, 128)
+    P["W2"][:] = rng.normal(0, scale * np.sqrt(2 / 128), (128, 128))
+    P["b2"][:] = rng.normal(0, 0.1, 128)
+    P["w3"][:] = rng.normal(0, 0.3 / np.sqrt(128), 128)
+    P["b3"][0] = np.log(np.expm1(s0))
+    return th.astype(np.float32).astype(np.float64)
+
+
+def _rows(seed, n):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 1, (n, 8))
+    X[:, 7] = 1.0
+    tau = 2.0 * X[:, 0] + rng.normal(0, 0.3, n)
+    return X.astype(np.float32), tau.astype(np.float32)
+
+
+def _mlp(th):
+    from paper_2602_02759_amd.nnef import Mlp as GMlp
+    return GMlp(to_dev(th.astype(np.float32)))
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("n", [1, 45, 1000, 8192])
+def test_forward_matches_oracle(n):
+    th = _params(1)
+    X, _ = _rows(2, n)
+    s = _mlp(th).forward(to_dev(X)).cpu().numpy()
+    ref, _ = Mlp.forward(th, X.astype(np.float64))
+    assert _rel(s, ref) <= 1e-2
+    assert np.all(np.abs(s - ref) <= 1e-2 * (np.abs(ref) + 0.1 * np.abs(ref).mean()))
+
+
+@pytest.mark.parametrize("n", [45, 1000, 20000])
+def test_gradient_matches_oracle(n):
+    th = _params(3)
+    X, tau = _rows(4, n)
+    g, l = _mlp(th).gradient(to_dev(X), to_dev(tau))
+    g = g.cpu().numpy()
+    lref, gref = Mlp.gradient(th, X.astype(np.float64), tau.astype(np.float64))
+    assert abs(l.item() - lref) <= 1e-2 * lref
+    o = 0
+    for name, shp in Mlp.SHAPES:
+        k = int(np.prod(shp))
+        r = _rel(g[o:o + k], gref[o:o + k])
+        print(f"n={n} {name}: rel {r:.2e}")
+        assert r <= 2e-2, (name, r)
+        o += k
+    assert _rel(g, gref) <= 1e-2
+
+
+def test_gradient_rows_by_index_is_exact():
+    """Rows selected through an index list give bit-identical gradients to
+    the same rows stored contiguously (fixed-order reduction)."""
+    import torch
+    th = _params(5)
+    X, tau = _rows(6, 3000)
+    idx = np.random.default_rng(7).permutation(3000)[:2500].astype(np.int32)
+    m = _mlp(th)
+    g1, l1 = m.gradient(to_dev(X), to_dev(tau), idx=to_dev(idx))
+    g2, l2 = m.gradient(to_dev(X[idx]), to_dev(tau[idx]))
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+    g3, _ = m.gradient(to_dev(X[idx]), to_dev(tau[idx]))
+    assert torch.equal(g2, g3)
+
+
+def test_adam_steps_match_oracle():
+    """Three Adam steps on the GPU equal the oracle's Adam applied to the GPU's
+    own gradients (FP32 arithmetic, 1e-5 of the step size)."""
+    th = _params(8)
+    X, tau = _rows(9, 4096)
+    Xd, td = to_dev(X), to_dev(tau)
+    m = _mlp(th)
+    lr = 1e-3
+    opt = Mlp.Adam(Mlp.N_PARAMS, lr=lr)
+    ref = m.params().cpu().numpy().astype(np.float64)
+    for _ in range(3):
+        g, _ = m.gradient(Xd, td)
+        ref = opt.step(ref, g.cpu().numpy().astype(np.float64))
+        m.train_step(Xd, td, lr)
+        got = m.params().cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-5 * lr * 10 + 1e-6 * np.max(np.abs(ref))
+
+
+def _cp_small(alpha=0.5, beta=1.0, seed=71):
+    return datagen.cp3(alpha, beta, sizes=dict(i=40, j=36, k=30), R=8, seed=seed)
+
+
+def _snapshots(plan, p, n):
+    """GPU iterates theta_0..theta_n (device) and their losses."""
+    import torch
+    Y = to_dev(p.Y)
+    M = to_dev(p.M) if p.M is not None else None
+    f = [to_dev(s) for s in clamp_init(p)]
+    snaps = [[t.clone() for t in f]]
+    tr = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    for s in range(n):
+        plan.step(Y, M, f, 1, loss_trace=tr[s:s + 1])
+        snaps.append([t.clone() for t in f])
+    plan.loss_device(Y, M, f, tr[n:n + 1])
+    return Y, M, snaps, tr.cpu().numpy()
+
+
+def test_rows_match_oracle():
+    import torch
+    from paper_2602_02759_amd.nnef import Plan
+    p = _cp_small()
+    plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, eps=EPS)
+    Y, M, snaps, losses = _snapshots(plan, p, 9)
+    t, h = 4, 5
+    n_el = sum(plan.numels)
+    X = torch.empty((n_el, 8), dtype=torch.float32, device="cuda")
+    tau = torch.empty(n_el, dtype=torch.float32, device="cuda")
+    rel = (losses[t - 1] - losses[t]) / losses[t]
+    plan.rows(snaps[t], snaps[t - 1], snaps[t - 2], snaps[t + h], rel, X, tau)
+    X, tau = X.cpu().numpy(), tau.cpu().numpy()
+    gamma = O.update_rule(p.alpha, p.beta)[1]
+    o = 0
+    for k, n in enumerate(plan.numels):
+        shape = snaps[0][k].shape
+        a, b, c, d = (snaps[j][k].cpu().numpy().astype(np.float64) for j in (t, t - 1, t - 2, t + h))
+        Xr, sig = Mlp.features(a, b, c, rel, gamma, EPS)
+        tr = Mlp.targets(a, d, sig)
+        np.testing.assert_allclose(X[o:o + n], Xr, rtol=1e-4, atol=2e-5)
+        np.testing.assert_allclose(tau[o:o + n], tr, rtol=1e-4, atol=2e-4)
+        assert shape[-1] == 8
+        o += n
+
+
+def _run_learned(plan, mlp, Y, M, init, n, P):
+    import torch
+    f = [t.clone() for t in init]
+    tr = torch.zeros(n, dtype=torch.float64, device="cuda")
+    acc = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.step_learned(mlp, Y, M, f, n, P, loss_trace=tr, n_accepted=acc)
+    torch.cuda.synchronize()
+    return f, tr.cpu().numpy(), int(acc.item())
+
+
+def test_rejected_proposals_leave_plain_sweeps_unchanged():
+    """A network with s = softplus(60) ~ 60 overshoots; every proposal must be
+    rejected and the result equals plain sweeps bit for bit."""
+    import torch
+    from paper_2602_02759_amd.nnef import Plan
+    p = _cp_small()
+    plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, eps=EPS)
+    th = np.zeros(Mlp.N_PARAMS)
+    Mlp.unpack(th)["b3"][0] = 60.0
+    Y = to_dev(p.Y)
+    M = to_dev(p.M)
+    init = [to_dev(s) for s in clamp_init(p)]
+    f, tr, acc = _run_learned(plan, _mlp(th), Y, M, init, 12, 4)
+    assert acc == 0
+    g = [t.clone() for t in init]
+    tr2 = torch.zeros(12, dtype=torch.float64, device="cuda")
+    plan.step(Y, M, g, 12, loss_trace=tr2)
+    for a, b in zip(f, g):
+        assert torch.equal(a, b)
+    np.testing.assert_array_equal(tr, tr2.cpu().numpy())
+
+
+def test_proposal_matches_oracle_and_accept_is_exact():
+    """One proposal after sweep 3 from a near-geometric network (s ~ 1): the
+    GPU result equals the oracle's proposal from the GPU's own iterates when
+    the oracle accepts it, else the plain iterate; the loss trace never
+    increases."""
+    import torch
+    from paper_2602_02759_amd.nnef import Plan
+    p = _cp_small(seed=72)
+    plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, eps=EPS)
+    th = _params(10, scale=0.2, s0=1.0)
+    Y, M, snaps, losses = _snapshots(plan, p, 3)
+    f, tr, acc = _run_learned(plan, _mlp(th), Y, M, snaps[0], 3, 3)
+    gamma = O.update_rule(p.alpha, p.beta)[1]
+    st = [[s[k].cpu().numpy().astype(np.float64) for k in range(3)] for s in snaps]
+    rel = (losses[2] - losses[3]) / losses[3]
+    prop = [Mlp.propose(th, st[3][k], st[2][k], st[1][k], rel, gamma, EPS) for k in range(3)]
+    l_prop = O.loss(p.model_str, prop, p.Y, p.M, p.alpha, p.beta)
+    l_cur = O.loss(p.model_str, st[3], p.Y, p.M, p.alpha, p.beta)
+    print(f"oracle: loss(theta_3) {l_cur:.8e} loss(proposal) {l_prop:.8e}; GPU accepted {acc}")
+    if abs(l_prop - l_cur) > 1e-3 * l_cur:  # the decision is not a near tie
+        assert acc == int(l_prop < l_cur)
+    if acc:
+        for k in range(3):
+            g = f[k].cpu().numpy().astype(np.float64)
+            assert _rel(g, prop[k]) <= 1e-2
+    else:
+        for k in range(3):
+            assert torch.equal(f[k], snaps[3][k])
+    assert np.all(np.diff(tr) <= 1e-6 * tr[:-1])

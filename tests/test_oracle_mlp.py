@@ -122,3 +122,10 @@ def test_accept_rule():
     assert not Mlp.accept(2.0, 2.0, c, 1e-10)       # equal loss: keep the iterate
     assert not Mlp.accept(3.0, 2.0, c, 1e-10)
     assert not Mlp.accept(1.0, 2.0, np.array([0.0, 1.0]), 1e-10)
+
+
+def test_targets_are_clipped():
+    th = np.array([1.0, 1.0])
+    tau = Mlp.targets(th, np.array([1e-10, 1.001]), 0.01)
+    assert tau[0] == -64.0
+    assert tau[1] == pytest.approx(np.log(1.001) / 0.01)
