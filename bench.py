@@ -40,6 +40,8 @@ def parse():
                     help="input precision of the N/D contractions")
     ap.add_argument("--cpu-sweeps", type=int, default=3,
                     help="oracle sweeps timed for the CPU baseline (0 disables)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and timing the learned extrapolation")
     ap.add_argument("--no-target", action="store_true",
                     help="skip the time-to-target comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -92,19 +94,20 @@ def load_target(alpha, beta):
 def run_to_target(phases, Y, M, init, target, chunk, max_sweeps):
     """Sweeps from ``init`` until the loss (FP32 terms, FP64 sums, taken at the
     start of every sweep inside the fused pass) is <= target.  ``phases`` is a
-    list of (name, plan); a phase ends when the target is met or its loss
-    stalls (relative decrease over a chunk < 1e-6), then the next one starts.
-    Returns the host wall time, including every sync and loss read-back."""
+    list of (name, run) with run(Y, M, factors, n_sweeps, loss_trace); a phase
+    ends when the target is met or its loss stalls (relative decrease over a
+    chunk < 1e-6), then the next one starts.  Returns the host wall time,
+    including every sync and loss read-back."""
     import torch
     f = [t.clone() for t in init]
     tr = torch.empty(chunk, dtype=torch.float64, device=Y.device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done, hit, per_phase, last = 0, None, {}, None
-    for pi, (name, plan) in enumerate(phases):
+    for pi, (name, run) in enumerate(phases):
         per_phase[name] = 0
         while done < max_sweeps and hit is None:
-            plan.step(Y, M, f, n_sweeps=chunk, loss_trace=tr)
+            run(Y, M, f, chunk, tr)
             trh = tr.cpu().numpy()
             idx = [i for i, v in enumerate(trh) if v <= target]
             if idx:
@@ -123,6 +126,15 @@ def run_to_target(phases, Y, M, init, target, chunk, max_sweeps):
     return {"wall_s": wall, "sweeps": hit, "reached": hit is not None, "sweeps_by_phase": per_phase}
 
 
+def plain(plan):
+    return lambda Y, M, f, n, tr: plan.step(Y, M, f, n_sweeps=n, loss_trace=tr)
+
+
+def with_proposals(plan, mlp, every, counter):
+    return lambda Y, M, f, n, tr: plan.step_learned(mlp, Y, M, f, n, every, loss_trace=tr,
+                                                    n_accepted=counter)
+
+
 def cpu_baseline(p, n_sweeps):
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -138,6 +150,47 @@ def cpu_baseline(p, n_sweeps):
     return {"value": n_sweeps / dt, "unit": "sweeps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_sweeps} full FP64 sweeps of the same workload after 1 warm-up "
                       f"({dt:.1f} s, numpy einsum on {os.cpu_count()} host CPUs)"}
+
+
+TRAIN_HORIZON = 8
+PROPOSE_EVERY = 5
+
+
+def train_extrapolator(n_sweeps=200):
+    """Train the extrapolation network on plain-MU trajectories of the NMF,
+    CP (both (alpha, beta)) and Tucker workloads, drawn with seeds other than
+    the benchmark's.  Returns the network and a summary."""
+    import numpy as np
+    import torch
+
+    from paper_2602_02759_amd import datagen, learned
+    from paper_2602_02759_amd.nnef import Mlp, Plan
+    t0 = time.perf_counter()
+    probs = [datagen.nmf_kl(seed=11), datagen.cp3(1.0, 1.0, seed=5), datagen.cp3(0.5, 1.0, seed=6),
+             datagen.tucker3(seed=13, I=256, J=256, K=64)]
+    t_gen = time.perf_counter() - t0
+    Xs, Ts = [], []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for p in probs:
+        plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta)
+        Y = torch.from_numpy(p.Y).cuda()
+        M = torch.from_numpy(p.M).cuda() if p.M is not None else None
+        init = [torch.from_numpy(np.maximum(t, 1e-10)).cuda() for t in p.init]
+        X, tau, _ = learned.trajectory_rows(plan, Y, M, init, n_sweeps, TRAIN_HORIZON, t_every=2)
+        Xs.append(X)
+        Ts.append(tau)
+        plan.close()
+    X, tau = torch.cat(Xs), torch.cat(Ts)
+    mlp = Mlp(learned.init_params(0, s0=float(TRAIN_HORIZON)))
+    l1 = learned.train(mlp, X, tau, 3000, batch=8192, lr=1e-3, seed=1)
+    l2 = learned.train(mlp, X, tau, 2000, batch=8192, lr=3e-4, seed=2)
+    torch.cuda.synchronize()
+    info = {"trajectories": [p.name for p in probs], "sweeps_each": n_sweeps,
+            "horizon": TRAIN_HORIZON, "rows": int(X.shape[0]), "adam_steps": 5000, "batch": 8192,
+            "row_loss_first": float(l1[:10].mean()), "row_loss_last": float(l2[-50:].mean()),
+            "gpu_s": time.perf_counter() - t1, "host_datagen_s": t_gen}
+    return mlp, info
 
 
 def main():
@@ -227,15 +280,30 @@ def main():
         thr = target * (1 + 1e-4)
         init = [torch.from_numpy(np.maximum(t, 1e-10)).to(dev) for t in p.init]
         plan16 = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, prec="bf16")
-        run_to_target([("fp32", plan)], Y, M, init, thr, 10, 60)  # warm-up
-        plain = run_to_target([("fp32", plan)], Y, M, init, thr, 10, 1000)
-        fast = run_to_target([("bf16", plan16), ("fp32", plan)], Y, M, init, thr, 10, 1000)
+        run_to_target([("fp32", plain(plan))], Y, M, init, thr, 10, 60)  # warm-up
+        arms = {"plain_fp32": [("fp32", plain(plan))],
+                "bf16": [("bf16", plain(plan16)), ("fp32", plain(plan))]}
+        info = None
+        if not args.no_learned:
+            mlp, info = train_extrapolator()
+            acc16 = torch.zeros(1, dtype=torch.int32, device=dev)
+            acc32 = torch.zeros(1, dtype=torch.int32, device=dev)
+            arms["bf16_learned"] = [("bf16", with_proposals(plan16, mlp, PROPOSE_EVERY, acc16)),
+                                    ("fp32", with_proposals(plan, mlp, PROPOSE_EVERY, acc32))]
+        res = {k: run_to_target(v, Y, M, init, thr, 10, 1000) for k, v in arms.items()}
+        if info is not None:
+            res["bf16_learned"]["proposals_accepted"] = int(acc16.item() + acc32.item())
+            res["bf16_learned"]["propose_every"] = PROPOSE_EVERY
+        base = res["plain_fp32"]
         out["time_to_target"] = {
             "L_star": target, "threshold": thr,
             "definition": "FP64 oracle loss after 200 plain sweeps from the seeded init; "
-                          "reached when the GPU loss <= L_star*(1+1e-4)",
-            "plain_fp32": plain, "bf16_then_fp32": fast,
-            "speedup": plain["wall_s"] / fast["wall_s"] if plain["reached"] and fast["reached"] else None}
+                          "reached when the GPU loss <= L_star*(1+1e-4); wall time includes "
+                          "every proposal, loss pass and accept test",
+            **res,
+            "speedup": {k: (base["wall_s"] / r["wall_s"] if base["reached"] and r["reached"] else None)
+                        for k, r in res.items() if k != "plain_fp32"},
+            "extrapolator_training": info}
     if args.cpu_sweeps > 0:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_sweeps)
     print(json.dumps(out), flush=True)

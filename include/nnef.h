@@ -234,6 +234,65 @@ nnef_status nnef_step_learned(nnef_plan_t plan, nnef_mlp_t mlp, const float* Y,
                               int propose_every, double* loss_trace, int* d_n_accepted,
                               void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched plans: many independent problems, each with several restarts (sets
+ * of factors sharing the problem's data), swept together.  Every block update
+ * of every run goes into one persistent launch per kernel class (contraction
+ * width, loss, layout), with the restarts of a problem interleaved so that they
+ * read each data tile at about the same time; one sweep over all runs is
+ * captured in a hipGraph and replayed.  Tile sizes per width class are chosen
+ * by nnef_batch_autotune.  Supported: models whose blocks need no materialised
+ * side operand or chain-back contraction (CP-like strings such as
+ * "ir,jr,kr,lr->ijkl"); others return NNEF_E_UNSUPPORTED.
+ * ------------------------------------------------------------------------ */
+typedef struct nnef_batch_s* nnef_batch_t;
+
+typedef struct {
+  const char* model_str;      /* as for nnef_plan */
+  const int64_t* mode_sizes;
+  int n_modes;
+  const int64_t* ranks;
+  int n_ranks;
+  double alpha, beta;
+  int n_restarts;             /* >= 1 factor sets sharing this problem's data */
+  int masked;                 /* 1 if a mask will be passed for this problem */
+} nnef_problem;
+
+/* Plan n_problems problems (options as for nnef_plan, shared).  Runs are
+ * numbered problem-major, restart-minor.  Allocates per-run partial buffers. */
+nnef_status nnef_batch_plan(const nnef_problem* problems, int n_problems, const nnef_options* opt,
+                            nnef_batch_t* out);
+void nnef_batch_destroy(nnef_batch_t batch);
+int nnef_batch_num_runs(nnef_batch_t batch);
+
+/*
+ * n_sweeps sweeps of Algorithm 1 for every run.
+ *   Y        : host array of n_problems device pointers (float32 data).
+ *   mask     : NULL, or host array of n_problems device pointers (uint8, NULL
+ *              entries for fully observed problems).
+ *   factors  : host array of device pointers, the L factor pointers of run 0,
+ *              then of run 1, ... (layouts as for nnef_step), updated in place.
+ *   loss_trace: NULL or device [n_sweeps][n_runs] doubles: the loss of every
+ *              run at the start of each sweep.
+ * The first call for a given set of pointers builds device argument tables and
+ * captures the sweep in a graph (the call synchronises then); later calls with
+ * the same pointers only replay it.  Enqueue only otherwise.
+ */
+nnef_status nnef_batch_step(nnef_batch_t batch, const float* const* Y, const uint8_t* const* mask,
+                            float* const* factors, int n_sweeps, double* loss_trace, void* stream);
+
+/*
+ * Autotuner: times the fused passes of every block for each candidate tiling
+ * (workgroups per run and pass, persistent grid size) on the given data, and
+ * keeps the fastest per contraction-width class.  Factors are not modified.
+ * Synchronises `stream`.
+ */
+nnef_status nnef_batch_autotune(nnef_batch_t batch, const float* const* Y, const uint8_t* const* mask,
+                                float* const* factors, void* stream);
+
+/* Lowering of every problem and the tiling chosen (as nnef_plan_describe). */
+size_t nnef_batch_describe(nnef_batch_t batch, char* buf, size_t buf_len);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* nnef_last_error(void);
 

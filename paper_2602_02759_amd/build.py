@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnnef.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "learned.hip", "fused16.hip", "fused32.hip", "fused64.hip", "planner.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "learned.hip", "fused16.hip", "fused32.hip", "fused64.hip",
+           "fused16b.hip", "fused32b.hip", "fused64b.hip", "planner.cpp", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel
@@ -26,8 +27,18 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", INCLUDE, "-I", CSRC]
 
 
-def _compile(src: str, defines=(), tag="") -> str:
+def _newest_header() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hs.append(os.path.join(INCLUDE, "nnef.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, defines=(), tag="", incremental=False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
+            return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
     cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], *lang, "-c", os.path.join(CSRC, src),
            "-o", obj]
@@ -37,12 +48,13 @@ def _compile(src: str, defines=(), tag="") -> str:
     return obj
 
 
-def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    """Compile and link; ``defines`` (e.g. ``["NNEF_PT32=4"]``) select tile variants."""
+def build(verbose: bool = False, out: str = LIB, defines=(), incremental: bool = False) -> str:
+    """Compile and link; ``defines`` (e.g. ``["NNEF_PT32=4"]``) select tile variants.
+    ``incremental`` reuses objects newer than their source and every header."""
     os.makedirs(BUILD, exist_ok=True)
     tag = "".join("." + d.replace("=", "_") for d in defines)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, defines, tag), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, defines, tag, incremental), SOURCES))
     tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,5 +67,5 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

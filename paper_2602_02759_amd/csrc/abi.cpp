@@ -124,9 +124,12 @@ static nnef_status upload_table(nnef_plan_s* p, const std::vector<uint32_t>& t, 
   return NNEF_OK;
 }
 
-nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_modes,
-                      const int64_t* ranks, int n_ranks, double alpha, double beta,
-                      const nnef_options* opt, nnef_plan_t* out) {
+// Plan set-up shared by nnef_plan and the batched plan.  with_pack: allocate
+// the buffer that holds the mask-packed data; target_wg: workgroups per pass.
+static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes, int n_modes,
+                               const int64_t* ranks, int n_ranks, double alpha, double beta,
+                               const nnef_options* opt, bool with_pack, int target_wg,
+                               nnef_plan_t* out, bool direct_only = false) {
   if (!model_str || !out) return fail(NNEF_E_ARG, "model_str and out must not be NULL");
   *out = nullptr;
   auto* p = new nnef_plan_s();
@@ -186,11 +189,10 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
     p->numel.push_back(n);
   }
   // ---- lowering of every block
-  const int target_wg = env_int("NNEF_TARGET_WG", 512);
   size_t part_elems = 0;
   for (int l = 0; l < (int)m.ops.size(); ++l) {
     BlockPlan bp;
-    Status st = lower_block(m, l, bp, p->ws_sizes, err);
+    Status st = lower_block(m, l, bp, p->ws_sizes, err, direct_only);
     if (st != ST_OK) {
       free_plan(p);
       return fail(st == ST_UNSUPPORTED ? NNEF_E_UNSUPPORTED : NNEF_E_SHAPE, err);
@@ -241,7 +243,7 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
       hipMalloc((void**)&p->loss_part, std::max(1, p->max_wg) * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&p->loss_tmp, sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&p->dcol, 64 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&p->ypack, (size_t)N * sizeof(float)) != hipSuccess) {
+      (with_pack && hipMalloc((void**)&p->ypack, (size_t)N * sizeof(float)) != hipSuccess)) {
     free_plan(p);
     return fail(NNEF_E_NOMEM, "partial-sum allocation failed");
   }
@@ -281,6 +283,13 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
   }
   *out = p;
   return NNEF_OK;
+}
+
+nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_modes,
+                      const int64_t* ranks, int n_ranks, double alpha, double beta,
+                      const nnef_options* opt, nnef_plan_t* out) {
+  return plan_create(model_str, mode_sizes, n_modes, ranks, n_ranks, alpha, beta, opt, true,
+                     env_int("NNEF_TARGET_WG", 512), out);
 }
 
 // ---------------------------------------------------------------------------
@@ -776,6 +785,523 @@ nnef_status nnef_step_learned(nnef_plan_t p, nnef_mlp_t q, const float* Y, const
     if (e) return hip_fail(e, "accept launch");
   }
   return NNEF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched plans: many problems and restarts in persistent launches
+struct BatchClass {
+  int KP = 0, wk = 0, prec = 0;
+  bool vecq = false, full = false;
+  int off = 0, n = 0, grid = 0;      // slice of the block's work array
+};
+
+struct BatchBlock {
+  std::vector<BatchClass> cls[2];     // by mode: 0 = N/D, 1 = N/D + loss (block 0)
+  FusedArgs* d_fargs[2] = {nullptr, nullptr};  // [n_runs]
+  WorkItem* d_work[2] = {nullptr, nullptr};
+  UpdateArgs* d_uargs[2] = {nullptr, nullptr};  // [n_runs]
+  int* d_colsum = nullptr;
+  int n_colsum = 0;
+  WorkItem* d_uwork = nullptr;
+  int n_uwork = 0;
+};
+
+struct nnef_batch_s {
+  std::vector<nnef_plan_s*> sub;      // one plan per problem: lowering and index tables
+  std::vector<int> restarts, masked;  // per problem
+  std::vector<int> run_prob, run_fac; // per run: problem, offset of its factor pointers
+  int n_runs = 0, n_fac_ptrs = 0, L_max = 0;
+  std::vector<float*> partN, partD, dcol;
+  std::vector<double*> lpart;
+  double* loss_slots = nullptr;       // [n_runs]
+  std::vector<BatchBlock> blocks;
+  int target[3] = {128, 128, 128};    // workgroups per run and pass, by width class 16/32/64
+  int grid[3] = {0, 0, 0};            // persistent grid per width class (0: one per item)
+  std::vector<const void*> bound;     // pointers the device tables were built for
+  hipStream_t cap = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::string tuning;
+};
+
+static int kp_class(int KP) { return KP == 16 ? 0 : KP == 32 ? 1 : 2; }
+
+static void drop_graphs(nnef_batch_s* b) {
+  for (int i = 0; i < 2; ++i) {
+    if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+    if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+    b->exec[i] = nullptr;
+    b->graph[i] = nullptr;
+  }
+}
+
+static void free_block_tables(BatchBlock& k) {
+  for (int m = 0; m < 2; ++m) {
+    for (void* q : {(void*)k.d_fargs[m], (void*)k.d_work[m], (void*)k.d_uargs[m]})
+      if (q) (void)hipFree(q);
+    k.d_fargs[m] = nullptr;
+    k.d_work[m] = nullptr;
+    k.d_uargs[m] = nullptr;
+    k.cls[m].clear();
+  }
+  for (void* q : {(void*)k.d_colsum, (void*)k.d_uwork})
+    if (q) (void)hipFree(q);
+  k.d_colsum = nullptr;
+  k.d_uwork = nullptr;
+}
+
+static void free_batch(nnef_batch_s* b) {
+  if (!b) return;
+  drop_graphs(b);
+  for (auto& k : b->blocks) free_block_tables(k);
+  for (auto v : {&b->partN, &b->partD, &b->dcol})
+    for (float* q : *v)
+      if (q) (void)hipFree(q);
+  for (double* q : b->lpart)
+    if (q) (void)hipFree(q);
+  if (b->loss_slots) (void)hipFree(b->loss_slots);
+  for (auto* q : b->sub) free_plan(q);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+void nnef_batch_destroy(nnef_batch_t b) { free_batch(b); }
+
+int nnef_batch_num_runs(nnef_batch_t b) { return b ? b->n_runs : 0; }
+
+// Geometry of every block of every problem for the current per-class targets.
+static bool batch_geometry(nnef_batch_s* b) {
+  for (auto* q : b->sub)
+    for (auto& bp : q->blocks)
+      if (!choose_geometry(q->m, bp, b->target[kp_class(bp.KP)])) return false;
+  return true;
+}
+
+}  // extern "C"
+
+template <class T>
+static nnef_status upload(T** d, const std::vector<T>& h) {
+  if (*d) (void)hipFree(*d);
+  *d = nullptr;
+  if (h.empty()) return NNEF_OK;
+  if (hipMalloc((void**)d, h.size() * sizeof(T)) != hipSuccess) return fail(NNEF_E_NOMEM, "table allocation failed");
+  if (hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(NNEF_E_DEVICE, "table upload failed");
+  return NNEF_OK;
+}
+
+extern "C" {
+
+// Device argument and work tables for the given data and factor pointers.
+static nnef_status batch_tables(nnef_batch_s* b, const float* const* Y, const uint8_t* const* M,
+                                float* const* factors) {
+  drop_graphs(b);
+  const int R = b->n_runs;
+  for (int l = 0; l < b->L_max; ++l) {
+    BatchBlock& k = b->blocks[l];
+    free_block_tables(k);
+    std::vector<UpdateArgs> ua[2];
+    ua[0].resize(R);
+    ua[1].resize(R);
+    std::vector<int> colsum;
+    std::vector<WorkItem> uwork;
+    for (int mode = 0; mode < (l == 0 ? 2 : 1); ++mode) {
+      std::vector<FusedArgs> fa(R);
+      std::memset(fa.data(), 0, R * sizeof(FusedArgs));
+      // class key -> items, ordered problem, workgroup, restart: the restarts of a
+      // problem read the same Y tile at about the same time (shared in the caches)
+      std::vector<BatchClass> cls;
+      std::vector<std::vector<WorkItem>> items;
+      int run0 = 0;
+      for (size_t pi = 0; pi < b->sub.size(); ++pi) {
+        nnef_plan_s* q = b->sub[pi];
+        const int nr = b->restarts[pi];
+        if (l < (int)q->blocks.size()) {
+          const BlockPlan& bp = q->blocks[l];
+          const bool msk = M && M[pi];
+          const float* Yd = msk ? q->ypack : Y[pi];
+          int ci = -1;
+          for (int r = 0; r < nr; ++r) {
+            const int run = run0 + r;
+            float* const* fr = factors + b->run_fac[run];
+            FusedArgs a = fused_args(q, bp, Yd, msk, fr);
+            a.partN = b->partN[run];
+            a.partD = b->partD[run];
+            a.loss_part = mode ? b->lpart[run] : nullptr;
+            a.xcd_remap = 0;
+            fa[run] = a;
+            if (r == 0) {
+              BatchClass c;
+              c.KP = bp.KP;
+              c.wk = q->ls.wk;
+              c.prec = a.prec;
+              c.vecq = bp.vecq;
+              c.full = a.full != 0;
+              for (size_t j = 0; j < cls.size(); ++j)
+                if (cls[j].KP == c.KP && cls[j].wk == c.wk && cls[j].prec == c.prec &&
+                    cls[j].vecq == c.vecq && cls[j].full == c.full)
+                  ci = (int)j;
+              if (ci < 0) {
+                ci = (int)cls.size();
+                cls.push_back(c);
+                items.emplace_back();
+              }
+            }
+            if (mode == 0) {
+              UpdateArgs u;
+              std::memset(&u, 0, sizeof(u));
+              u.partN = b->partN[run];
+              u.partD = b->partD[run];
+              u.n_chunks = bp.n_chunks;
+              u.nP = (int)bp.nP;
+              u.K = bp.K;
+              u.KP = bp.KP;
+              u.no_d = a.no_d;
+              u.npieces = (int)bp.pieces.size();
+              for (int i = 0; i < u.npieces; ++i) {
+                u.piece[i] = piece_ptr(q, bp.pieces[i], fr);
+                u.ldpiece[i] = bp.pieces[i].ld;
+                u.nrows[i] = bp.pieces[i].nrows;
+              }
+              u.theta = fr[l];
+              u.ldT = bp.ldL;
+              u.upd = q->ls.upd;
+              u.gamma = (float)q->ls.gamma;
+              u.eps = (float)q->opt.eps;
+              u.dcol = b->dcol[run];
+              ua[0][run] = u;
+              u.loss_part = b->lpart[run];
+              u.n_loss_part = bp.n_wg;
+              u.loss_out = b->loss_slots + run;
+              ua[1][run] = u;
+              if (a.no_d) colsum.push_back(run);
+              const int nb = (int)((bp.nP * bp.K + 63) / 64);
+              for (int j = 0; j < nb; ++j) uwork.push_back(WorkItem{run, j});
+            }
+          }
+          for (int w = 0; w < bp.n_wg; ++w)
+            for (int r = 0; r < nr; ++r) items[ci].push_back(WorkItem{run0 + r, w});
+        }
+        run0 += nr;
+      }
+      std::vector<WorkItem> all;
+      for (size_t j = 0; j < cls.size(); ++j) {
+        cls[j].off = (int)all.size();
+        cls[j].n = (int)items[j].size();
+        const int g = b->grid[kp_class(cls[j].KP)];
+        cls[j].grid = g > 0 ? std::min(g, cls[j].n) : cls[j].n;
+        all.insert(all.end(), items[j].begin(), items[j].end());
+      }
+      k.cls[mode] = cls;
+      nnef_status st = upload(&k.d_fargs[mode], fa);
+      if (st == NNEF_OK) st = upload(&k.d_work[mode], all);
+      if (st != NNEF_OK) return st;
+    }
+    nnef_status st = upload(&k.d_uargs[0], ua[0]);
+    if (st == NNEF_OK && l == 0) st = upload(&k.d_uargs[1], ua[1]);
+    if (st == NNEF_OK) st = upload(&k.d_colsum, colsum);
+    if (st == NNEF_OK) st = upload(&k.d_uwork, uwork);
+    if (st != NNEF_OK) return st;
+    k.n_colsum = (int)colsum.size();
+    k.n_uwork = (int)uwork.size();
+  }
+  b->bound.clear();
+  for (size_t pi = 0; pi < b->sub.size(); ++pi) {
+    b->bound.push_back(Y[pi]);
+    b->bound.push_back(M ? (const void*)M[pi] : nullptr);
+  }
+  for (int i = 0; i < b->n_fac_ptrs; ++i) b->bound.push_back(factors[i]);
+  return NNEF_OK;
+}
+
+// One sweep over every run (the launch sequence that is captured in a graph).
+static nnef_status batch_sweep(nnef_batch_s* b, bool with_loss, hipStream_t s) {
+  for (int l = 0; l < b->L_max; ++l) {
+    BatchBlock& k = b->blocks[l];
+    const int mode = (with_loss && l == 0) ? 1 : 0;
+    for (const BatchClass& c : k.cls[mode]) {
+      BatchedLaunch L;
+      L.args = k.d_fargs[mode];
+      L.work = k.d_work[mode] + c.off;
+      L.n_work = c.n;
+      L.grid = c.grid;
+      L.KP = c.KP;
+      L.wk = c.wk;
+      L.mode = mode;
+      L.prec = c.prec;
+      L.vecq = c.vecq;
+      L.full = c.full;
+      const int e = launch_fused_batched(L, s);
+      if (e) return hip_fail(e, "batched fused pass launch");
+    }
+    const int ugrid = std::min(k.n_uwork, 4096);
+    const int e = launch_update_batched(k.d_uargs[mode], k.d_colsum, k.n_colsum, k.d_uwork, k.n_uwork,
+                                        ugrid, s);
+    if (e) return hip_fail(e, "batched update launch");
+  }
+  return NNEF_OK;
+}
+
+nnef_status nnef_batch_plan(const nnef_problem* probs, int n_problems, const nnef_options* opt,
+                            nnef_batch_t* out) {
+  if (!probs || n_problems <= 0 || !out) return fail(NNEF_E_ARG, "problems, n_problems and out must be valid");
+  *out = nullptr;
+  auto* b = new nnef_batch_s();
+  for (int pi = 0; pi < n_problems; ++pi) {
+    const nnef_problem& d = probs[pi];
+    if (d.n_restarts < 1) {
+      free_batch(b);
+      return fail(NNEF_E_ARG, "n_restarts must be >= 1");
+    }
+    nnef_plan_t q = nullptr;
+    nnef_status st = plan_create(d.model_str, d.mode_sizes, d.n_modes, d.ranks, d.n_ranks, d.alpha,
+                                 d.beta, opt, d.masked != 0, 128, &q, true);
+    if (st != NNEF_OK) {
+      free_batch(b);
+      return fail(st, "problem " + std::to_string(pi) + ": " + g_last_error);
+    }
+    b->sub.push_back(q);
+    for (const BlockPlan& bp : q->blocks)
+      if (!bp.L_direct || !bp.L_prog.empty() || !bp.R_prog.empty() || !bp.chainN.empty()) {
+        free_batch(b);
+        return fail(NNEF_E_UNSUPPORTED, "problem " + std::to_string(pi) +
+                                            ": batched plans take models whose blocks need no side "
+                                            "operands or chain-back (CP-like strings)");
+      }
+    b->restarts.push_back(d.n_restarts);
+    b->masked.push_back(d.masked != 0);
+    const int L = (int)q->m.ops.size();
+    b->L_max = std::max(b->L_max, L);
+    for (int r = 0; r < d.n_restarts; ++r) {
+      b->run_prob.push_back(pi);
+      b->run_fac.push_back(b->n_fac_ptrs);
+      b->n_fac_ptrs += L;
+      ++b->n_runs;
+    }
+  }
+  // partial buffers per run, sized for the largest tiling the autotuner tries
+  const int cand[3] = {32, 128, 512};
+  size_t run0 = 0;
+  for (size_t pi = 0; pi < b->sub.size(); ++pi) {
+    nnef_plan_s* q = b->sub[pi];
+    size_t part = 1;
+    int wg = 1;
+    for (int t : cand)
+      for (BlockPlan bp : q->blocks) {
+        if (!choose_geometry(q->m, bp, t)) {
+          free_batch(b);
+          return fail(NNEF_E_SHAPE, "grid too large");
+        }
+        part = std::max(part, (size_t)bp.n_chunks * bp.nP * bp.KP);
+        wg = std::max(wg, bp.n_wg);
+      }
+    if (part >= (size_t(1) << 30)) {
+      free_batch(b);
+      return fail(NNEF_E_SHAPE, "partial sums need 2^30 or more elements");
+    }
+    for (int r = 0; r < b->restarts[pi]; ++r) {
+      float *pn = nullptr, *pd = nullptr, *dc = nullptr;
+      double* lp = nullptr;
+      const bool ok = hipMalloc((void**)&pn, part * sizeof(float)) == hipSuccess &&
+                      hipMalloc((void**)&pd, part * sizeof(float)) == hipSuccess &&
+                      hipMalloc((void**)&dc, 64 * sizeof(float)) == hipSuccess &&
+                      hipMalloc((void**)&lp, wg * sizeof(double)) == hipSuccess;
+      b->partN.push_back(pn);
+      b->partD.push_back(pd);
+      b->dcol.push_back(dc);
+      b->lpart.push_back(lp);
+      if (!ok) {
+        free_batch(b);
+        return fail(NNEF_E_NOMEM, "per-run buffer allocation failed");
+      }
+    }
+    run0 += b->restarts[pi];
+  }
+  if (hipMalloc((void**)&b->loss_slots, b->n_runs * sizeof(double)) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    free_batch(b);
+    return fail(NNEF_E_DEVICE, "batch set-up failed");
+  }
+  b->blocks.resize(b->L_max);
+  if (!batch_geometry(b)) {
+    free_batch(b);
+    return fail(NNEF_E_SHAPE, "grid too large");
+  }
+  *out = b;
+  return NNEF_OK;
+}
+
+static bool same_binding(const nnef_batch_s* b, const float* const* Y, const uint8_t* const* M,
+                         float* const* factors) {
+  if (b->bound.size() != 2 * b->sub.size() + (size_t)b->n_fac_ptrs) return false;
+  size_t i = 0;
+  for (size_t pi = 0; pi < b->sub.size(); ++pi) {
+    if (b->bound[i++] != Y[pi]) return false;
+    if (b->bound[i++] != (M ? (const void*)M[pi] : nullptr)) return false;
+  }
+  for (int f = 0; f < b->n_fac_ptrs; ++f)
+    if (b->bound[i++] != factors[f]) return false;
+  return true;
+}
+
+static nnef_status batch_check(nnef_batch_s* b, const float* const* Y, const uint8_t* const* M,
+                               float* const* factors) {
+  if (!b || !Y || !factors) return fail(NNEF_E_ARG, "batch, Y and factors must not be NULL");
+  for (size_t pi = 0; pi < b->sub.size(); ++pi) {
+    if (!Y[pi]) return fail(NNEF_E_ARG, "Y pointer is NULL");
+    if (M && M[pi] && !b->masked[pi])
+      return fail(NNEF_E_ARG, "problem " + std::to_string(pi) + " was planned without a mask");
+  }
+  for (int f = 0; f < b->n_fac_ptrs; ++f)
+    if (!factors[f]) return fail(NNEF_E_ARG, "factor pointer is NULL");
+  return NNEF_OK;
+}
+
+static nnef_status batch_pack(nnef_batch_s* b, const float* const* Y, const uint8_t* const* M,
+                              hipStream_t s) {
+  if (!M) return NNEF_OK;
+  for (size_t pi = 0; pi < b->sub.size(); ++pi)
+    if (M[pi]) {
+      const int e = launch_pack(Y[pi], M[pi], b->sub[pi]->ypack, b->sub[pi]->n_data, s);
+      if (e) return hip_fail(e, "data packing launch");
+    }
+  return NNEF_OK;
+}
+
+nnef_status nnef_batch_step(nnef_batch_t b, const float* const* Y, const uint8_t* const* M,
+                            float* const* factors, int n_sweeps, double* loss_trace, void* stream) {
+  nnef_status st = batch_check(b, Y, M, factors);
+  if (st != NNEF_OK) return st;
+  if (n_sweeps < 0) return fail(NNEF_E_ARG, "n_sweeps must be >= 0");
+  if (n_sweeps == 0) return NNEF_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (!same_binding(b, Y, M, factors)) {
+    st = batch_tables(b, Y, M, factors);
+    if (st != NNEF_OK) return st;
+  }
+  st = batch_pack(b, Y, M, s);
+  if (st != NNEF_OK) return st;
+  const int gi = loss_trace ? 1 : 0;
+  if (!b->exec[gi]) {
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(NNEF_E_DEVICE, "graph capture could not start");
+    st = batch_sweep(b, gi == 1, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != NNEF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess || !g) return hip_fail(e, "graph capture");
+    b->graph[gi] = g;
+    if (hipGraphInstantiate(&b->exec[gi], g, nullptr, nullptr, 0) != hipSuccess) {
+      b->exec[gi] = nullptr;
+      return fail(NNEF_E_DEVICE, "graph instantiation failed");
+    }
+  }
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    const hipError_t e = hipGraphLaunch(b->exec[gi], s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    if (loss_trace) {
+      const int ec = launch_copy_f64(loss_trace + (size_t)sw * b->n_runs, b->loss_slots, b->n_runs, s);
+      if (ec) return hip_fail(ec, "loss copy launch");
+    }
+  }
+  return NNEF_OK;
+}
+
+nnef_status nnef_batch_autotune(nnef_batch_t b, const float* const* Y, const uint8_t* const* M,
+                                float* const* factors, void* stream) {
+  nnef_status st = batch_check(b, Y, M, factors);
+  if (st != NNEF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = batch_pack(b, Y, M, s);
+  if (st != NNEF_OK) return st;
+  struct Cand {
+    int target, grid;
+  };
+  const Cand cands[] = {{32, 0}, {128, 0}, {512, 0}, {32, 1024}, {128, 1024}, {512, 1024},
+                        {128, 2048}, {512, 2048}};
+  double best[3] = {1e300, 1e300, 1e300};
+  Cand pick[3] = {{128, 0}, {128, 0}, {128, 0}};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(NNEF_E_DEVICE, "event creation failed");
+  for (const Cand& c : cands) {
+    for (int i = 0; i < 3; ++i) {
+      b->target[i] = c.target;
+      b->grid[i] = c.grid;
+    }
+    if (!batch_geometry(b)) continue;
+    st = batch_tables(b, Y, M, factors);
+    if (st != NNEF_OK) break;
+    double t[3] = {0, 0, 0};
+    for (int rep = 0; rep < 2; ++rep) {
+      double tr[3] = {0, 0, 0};
+      for (int l = 0; l < b->L_max; ++l)
+        for (const BatchClass& k : b->blocks[l].cls[0]) {
+          BatchedLaunch L;
+          L.args = b->blocks[l].d_fargs[0];
+          L.work = b->blocks[l].d_work[0] + k.off;
+          L.n_work = k.n;
+          L.grid = k.grid;
+          L.KP = k.KP;
+          L.wk = k.wk;
+          L.mode = 0;
+          L.prec = k.prec;
+          L.vecq = k.vecq;
+          L.full = k.full;
+          float ms = 0.f;
+          if (hipEventRecord(e0, s) != hipSuccess || launch_fused_batched(L, s) ||
+              hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return fail(NNEF_E_DEVICE, "autotune timing failed");
+          }
+          tr[kp_class(k.KP)] += ms;
+        }
+      for (int i = 0; i < 3; ++i) t[i] = rep == 0 ? tr[i] : std::min(t[i], tr[i]);
+    }
+    for (int i = 0; i < 3; ++i)
+      if (t[i] < best[i]) {
+        best[i] = t[i];
+        pick[i] = c;
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != NNEF_OK) return st;
+  b->tuning.clear();
+  const char* names[3] = {"16", "32", "64"};
+  for (int i = 0; i < 3; ++i) {
+    b->target[i] = pick[i].target;
+    b->grid[i] = pick[i].grid;
+    if (best[i] > 0 && best[i] < 1e300)
+      b->tuning += std::string("width ") + names[i] + ": " + std::to_string(pick[i].target) +
+                   " workgroups per run, grid " +
+                   (pick[i].grid ? std::to_string(pick[i].grid) : std::string("all items")) + ", " +
+                   std::to_string(best[i]) + " ms per sweep of fused passes\n";
+  }
+  if (!batch_geometry(b)) return fail(NNEF_E_SHAPE, "grid too large");
+  st = batch_tables(b, Y, M, factors);
+  if (st != NNEF_OK) return st;
+  return hipStreamSynchronize(s) == hipSuccess ? NNEF_OK : fail(NNEF_E_DEVICE, "sync failed");
+}
+
+size_t nnef_batch_describe(nnef_batch_t b, char* buf, size_t n) {
+  if (!b) return 0;
+  std::string d = std::to_string(b->sub.size()) + " problems, " + std::to_string(b->n_runs) + " runs\n";
+  for (size_t pi = 0; pi < b->sub.size(); ++pi)
+    d += "problem " + std::to_string(pi) + " x" + std::to_string(b->restarts[pi]) + ":\n" +
+         b->sub[pi]->description;
+  d += b->tuning;
+  if (buf && n) {
+    const size_t k = std::min(n - 1, d.size());
+    std::memcpy(buf, d.data(), k);
+    buf[k] = 0;
+  }
+  return d.size();
 }
 
 }  // extern "C"

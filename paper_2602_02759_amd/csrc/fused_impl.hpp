@@ -222,8 +222,10 @@ __device__ __forceinline__ void store_partial(const f4 (&acc)[Tile<KP>::PT][Tile
   __syncthreads();
 }
 
+// One workgroup's tile: braw is the workgroup index within the problem's
+// grid (before the XCD remap), slot its loss-partial index.
 template <int KP, int WK, bool VECQ, int MODE, bool FULL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_pass(FusedArgs a) {
+__device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, int slot) {
   using T = Tile<KP>;
   constexpr int PT = T::PT, ROWS = T::ROWS, KS = T::KS, KT = T::KT, RST = T::RST;
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, c = lane & 15;
-  int b = blockIdx.x;
+  int b = braw;
   if (a.xcd_remap) b = (b & 7) * (a.n_wg >> 3) + (b >> 3);
   const int panel = b % a.n_panels, chunk = b / a.n_panels;
   const int p0 = panel * ROWS;
@@ -548,7 +550,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const double w = wave_sum(lsum);
     if (lane == 0) lred[wave] = w;
     __syncthreads();
-    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+    if (threadIdx.x == 0) a.loss_part[slot] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
   }
   if constexpr (ND) {
     store_partial<KP>(accN, a.partN, red, a, wave, g, c, p0, chunk);
@@ -556,6 +558,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+template <int KP, int WK, bool VECQ, int MODE, bool FULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_pass(FusedArgs a) {
+  fused_pass_body<KP, WK, VECQ, MODE, FULL>(a, blockIdx.x, blockIdx.x);
+}
+
+// Persistent form over many problems (see fused_x32_batched).
+template <int KP, int WK, bool VECQ, int MODE, bool FULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_pass_batched(
+    const FusedArgs* __restrict__ args, const WorkItem* __restrict__ work, int n_work) {
+  for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const WorkItem it = work[w];
+    const FusedArgs a = args[it.run];
+    fused_pass_body<KP, WK, VECQ, MODE, FULL>(a, it.blk, it.blk);
+    __syncthreads();
+  }
+}
+
+#ifndef NNEF_BATCHED_TU
 template <int KP, int WK, bool VECQ, int MODE>
 int launch_fused_t(const FusedArgs& a, hipStream_t s) {
   if (a.full)
@@ -591,5 +611,37 @@ int launch_fused_w(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t 
   }
 }
 
+#else
+template <int KP, int WK, bool VECQ, int MODE>
+int launch_fused_batched_t(const BatchedLaunch& L, hipStream_t s) {
+  if (L.full)
+    hipLaunchKernelGGL((fused_pass_batched<KP, WK, VECQ, MODE, true>), dim3(L.grid), dim3(256), 0, s,
+                       L.args, L.work, L.n_work);
+  else
+    hipLaunchKernelGGL((fused_pass_batched<KP, WK, VECQ, MODE, false>), dim3(L.grid), dim3(256), 0, s,
+                       L.args, L.work, L.n_work);
+  return (int)hipGetLastError();
+}
+
+template <int KP, int WK>
+int launch_fused_batched_v(const BatchedLaunch& L, hipStream_t s) {
+  if (L.vecq)
+    return L.mode ? launch_fused_batched_t<KP, WK, true, 1>(L, s) : launch_fused_batched_t<KP, WK, true, 0>(L, s);
+  return L.mode ? launch_fused_batched_t<KP, WK, false, 1>(L, s) : launch_fused_batched_t<KP, WK, false, 0>(L, s);
+}
+
+template <int KP>
+int launch_fused_batched_w(const BatchedLaunch& L, hipStream_t s) {
+  switch (L.wk) {
+    case WK_KL: return launch_fused_batched_v<KP, WK_KL>(L, s);
+    case WK_EUC: return launch_fused_batched_v<KP, WK_EUC>(L, s);
+    case WK_SQRT: return launch_fused_batched_v<KP, WK_SQRT>(L, s);
+    case WK_IS: return launch_fused_batched_v<KP, WK_IS>(L, s);
+    case WK_GEN: return launch_fused_batched_v<KP, WK_GEN>(L, s);
+    default: return launch_fused_batched_v<KP, WK_RKL>(L, s);
+  }
+}
+
+#endif
 }  // namespace
 }  // namespace nnef

@@ -51,9 +51,10 @@ __device__ __forceinline__ f16v mfma_lp(const float* av, const float* bv, const 
 
 // PREC: input precision of the numerator/denominator contractions
 // (0 = FP32, 1 = BF16, 2 = FP16); the reconstruction is always FP32.
+// One workgroup's tile: braw is the workgroup index within the problem's
+// grid (before the XCD remap), slot its loss-partial index.
 template <int WK, bool VECQ, int MODE, bool FULL, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_x32(
-    FusedArgs a) {
+__device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int slot) {
   constexpr int KP = 32, ROWS = 32, RST = KP + 4;
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
   // Y ring for the direct-to-LDS prefetch of full tiles: kStages stages of 4 KB
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 5, c = lane & 31;
-  int b = blockIdx.x;
+  int b = braw;
   if (a.xcd_remap) b = (b & 7) * (a.n_wg >> 3) + (b >> 3);
   const int panel = b % a.n_panels, chunk = b / a.n_panels;
   const int p0 = panel * ROWS;
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const double w = wave_sum(lsum);
     if (lane == 0) lred[wave] = w;
     __syncthreads();
-    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+    if (threadIdx.x == 0) a.loss_part[slot] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
   }
   if constexpr (ND) {
     // accumulator register v holds X^T[k = 8(v/4) + 4g + v%4][p = p0 + c]; waves
@@ -438,6 +439,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+template <int WK, bool VECQ, int MODE, bool FULL, int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_x32(
+    FusedArgs a) {
+  fused_x32_body<WK, VECQ, MODE, FULL, PREC>(a, blockIdx.x, blockIdx.x);
+}
+
+// Persistent form over many problems: work item w = (problem, workgroup index
+// in that problem's grid); each workgroup walks the items w = blockIdx.x,
+// blockIdx.x + gridDim.x, ...
+template <int WK, bool VECQ, int MODE, bool FULL, int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_x32_batched(
+    const FusedArgs* __restrict__ args, const WorkItem* __restrict__ work, int n_work) {
+  for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const WorkItem it = work[w];
+    const FusedArgs a = args[it.run];
+    fused_x32_body<WK, VECQ, MODE, FULL, PREC>(a, it.blk, it.blk);
+    __syncthreads();
+  }
+}
+
+#ifndef NNEF_BATCHED_TU
 template <int WK, bool VECQ, int MODE, int PREC>
 int launch_x32_p(const FusedArgs& a, hipStream_t s) {
   if (a.full)
@@ -481,5 +503,43 @@ int launch_x32(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
   }
 }
 
+#else
+template <int WK, bool VECQ, int MODE, int PREC>
+int launch_x32_batched_p(const BatchedLaunch& L, hipStream_t s) {
+  if (L.full)
+    hipLaunchKernelGGL((fused_x32_batched<WK, VECQ, MODE, true, PREC>), dim3(L.grid), dim3(256), 0, s,
+                       L.args, L.work, L.n_work);
+  else
+    hipLaunchKernelGGL((fused_x32_batched<WK, VECQ, MODE, false, PREC>), dim3(L.grid), dim3(256), 0,
+                       s, L.args, L.work, L.n_work);
+  return (int)hipGetLastError();
+}
+
+template <int WK, bool VECQ, int MODE>
+int launch_x32_batched_m(const BatchedLaunch& L, hipStream_t s) {
+  if (L.prec == 0) return launch_x32_batched_p<WK, VECQ, MODE, 0>(L, s);
+  if (L.prec == 1) return launch_x32_batched_p<WK, VECQ, MODE, 1>(L, s);
+  return launch_x32_batched_p<WK, VECQ, MODE, 2>(L, s);
+}
+
+template <int WK>
+int launch_x32_batched_w(const BatchedLaunch& L, hipStream_t s) {
+  if (L.vecq)
+    return L.mode ? launch_x32_batched_m<WK, true, 1>(L, s) : launch_x32_batched_m<WK, true, 0>(L, s);
+  return L.mode ? launch_x32_batched_m<WK, false, 1>(L, s) : launch_x32_batched_m<WK, false, 0>(L, s);
+}
+
+int launch_x32_batched(const BatchedLaunch& L, hipStream_t s) {
+  switch (L.wk) {
+    case WK_KL: return launch_x32_batched_w<WK_KL>(L, s);
+    case WK_EUC: return launch_x32_batched_w<WK_EUC>(L, s);
+    case WK_SQRT: return launch_x32_batched_w<WK_SQRT>(L, s);
+    case WK_IS: return launch_x32_batched_w<WK_IS>(L, s);
+    case WK_GEN: return launch_x32_batched_w<WK_GEN>(L, s);
+    default: return launch_x32_batched_w<WK_RKL>(L, s);
+  }
+}
+
+#endif
 }  // namespace
 }  // namespace nnef

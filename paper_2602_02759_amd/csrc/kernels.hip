@@ -15,6 +15,9 @@ namespace nnef {
 int launch_fused_kp16(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s);
 int launch_fused_kp32(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s);
 int launch_fused_kp64(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s);
+int launch_fused_batched_kp16(const BatchedLaunch& L, hipStream_t s);
+int launch_fused_batched_kp32(const BatchedLaunch& L, hipStream_t s);
+int launch_fused_batched_kp64(const BatchedLaunch& L, hipStream_t s);
 
 namespace {
 __device__ __forceinline__ double wave_sum(double v) {
@@ -40,7 +43,7 @@ __device__ __forceinline__ float mu_rule(float th, float n, float d, int upd, fl
   return fmaxf(eps, th * s);
 }
 
-__global__ __launch_bounds__(256) void colsum_kernel(UpdateArgs a, float* dcol) {
+__device__ __forceinline__ void colsum_body(const UpdateArgs& a, float* dcol) {
   // dcol[k] = prod_m sum_rows piece_m[row][k]; one workgroup, K <= 64
   __shared__ double part[4][64];
   const int k = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -57,14 +60,16 @@ __global__ __launch_bounds__(256) void colsum_kernel(UpdateArgs a, float* dcol) 
   if (w == 0 && k < a.K) dcol[k] = (float)prod;
 }
 
+__global__ __launch_bounds__(256) void colsum_kernel(UpdateArgs a, float* dcol) { colsum_body(a, dcol); }
+
 // One workgroup per 64 consecutive (p, k) outputs; its four waves sum
 // interleaved quarters of the partial slots, then wave 0 adds the quarters in a
 // fixed order (deterministic) and applies the update.
-__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, const float* dcol) {
+__device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dcol, int blk) {
   __shared__ double sN[4][64], sD[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t n = (int64_t)a.nP * a.K;
-  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t idx = (int64_t)blk * 64 + lane;
   const bool valid = idx < n;
   const int p = valid ? (int)(idx / a.K) : 0, k = valid ? (int)(idx % a.K) : 0;
   double N = 0.0, D = 0.0;
@@ -105,11 +110,31 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, const float* 
       a.DL[idx] = (float)D;
     }
   }
-  if (a.loss_out && blockIdx.x == 0 && w == 1) {
+  if (a.loss_out && blk == 0 && w == 1) {
     double sl = 0.0;
     for (int i = lane; i < a.n_loss_part; i += 64) sl += a.loss_part[i];
     sl = wave_sum(sl);
     if (lane == 0) *a.loss_out = sl;
+  }
+}
+
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, const float* dcol) {
+  update_body(a, dcol, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void colsum_batched(const UpdateArgs* __restrict__ args,
+                                                      const int* __restrict__ runs) {
+  const UpdateArgs a = args[runs[blockIdx.x]];
+  colsum_body(a, a.dcol);
+}
+
+__global__ __launch_bounds__(256) void update_batched(const UpdateArgs* __restrict__ args,
+                                                      const WorkItem* __restrict__ work, int n_work) {
+  for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const WorkItem it = work[w];
+    const UpdateArgs a = args[it.run];
+    update_body(a, a.dcol, it.blk);
+    __syncthreads();
   }
 }
 
@@ -176,6 +201,11 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Y,
   }
 }
 
+__global__ __launch_bounds__(256) void copy_f64_kernel(double* dst, const double* src, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 __global__ __launch_bounds__(256) void zero_kernel(float* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
@@ -195,6 +225,17 @@ int launch_fused(const FusedArgs& a, int KP, int wk, bool vecq, int mode, void* 
   }
 }
 
+int launch_fused_batched(const BatchedLaunch& L, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (L.n_work <= 0) return 0;
+  switch (L.KP) {
+    case 16: return launch_fused_batched_kp16(L, s);
+    case 32: return launch_fused_batched_kp32(L, s);
+    case 64: return launch_fused_batched_kp64(L, s);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
 int launch_update(const UpdateArgs& a, float* dcol, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (a.no_d) {
@@ -206,6 +247,14 @@ int launch_update(const UpdateArgs& a, float* dcol, void* stream) {
   return (int)hipGetLastError();
 }
 
+
+int launch_update_batched(const UpdateArgs* args, const int* colsum_runs, int n_colsum,
+                          const WorkItem* work, int n_work, int grid, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (n_colsum > 0) hipLaunchKernelGGL(colsum_batched, dim3(n_colsum), dim3(256), 0, s, args, colsum_runs);
+  if (n_work > 0) hipLaunchKernelGGL(update_batched, dim3(grid), dim3(256), 0, s, args, work, n_work);
+  return (int)hipGetLastError();
+}
 
 int launch_einsum(const EinsumArgs& a, void* stream) {
   if (a.n_out_total <= 0) return 0;
@@ -231,6 +280,13 @@ int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* st
   const int64_t threads = (n + 3) / 4;
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
                      (hipStream_t)stream, Y, M, Yp, n);
+  return (int)hipGetLastError();
+}
+
+int launch_copy_f64(double* dst, const double* src, int n, void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, dst, src, n);
   return (int)hipGetLastError();
 }
 

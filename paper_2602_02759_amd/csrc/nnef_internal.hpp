@@ -102,6 +102,7 @@ struct UpdateArgs {
   int upd; float gamma; float eps;
   // loss finalisation (first block of a sweep)
   const double* loss_part; int n_loss_part; double* loss_out;
+  float* dcol;                 // [K] closed-form D scratch (no_d)
 };
 
 // Generic n-ary contraction out[o] = sum_c prod_i in_i[...] over explicit strides.
@@ -128,11 +129,30 @@ struct ApplyArgs {
 // Launchers (kernels.hip).  Return 0 or a hipError_t value.
 // mode: 0 = N, D only; 1 = N, D and the loss; 2 = the loss only
 int launch_fused(const FusedArgs& a, int KP, int wk, bool vecq, int mode, void* stream);
+
+// Persistent launch over many problems ("runs"): work item = (run, workgroup
+// index within that run's grid); args[run] holds the run's FusedArgs.
+struct WorkItem {
+  int run, blk;
+};
+struct BatchedLaunch {
+  const FusedArgs* args;   // device
+  const WorkItem* work;    // device
+  int n_work, grid;
+  int KP, wk, mode, prec;  // mode 0: N/D, 1: N/D + loss
+  bool vecq, full;
+};
+int launch_fused_batched(const BatchedLaunch& L, void* stream);
 int launch_update(const UpdateArgs& a, float* dcol, void* stream);  // dcol: [K] scratch for a closed-form D
+// Many runs: colsum over runs[0..n_colsum) (one workgroup each, those with
+// no_d), then the update over the work items (run, 64-output block).
+int launch_update_batched(const UpdateArgs* args, const int* colsum_runs, int n_colsum,
+                          const WorkItem* work, int n_work, int grid, void* stream);
 int launch_einsum(const EinsumArgs& a, void* stream);
 int launch_apply(const ApplyArgs& a, void* stream);
 int launch_loss_final(const double* part, int n, double* out, void* stream);
 int launch_zero(float* p, int64_t n, void* stream);
+int launch_copy_f64(double* dst, const double* src, int n, void* stream);
 // Yp[i] = mask[i] ? Y[i] : -1 (observed data are nonnegative).
 int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream);
 

@@ -227,7 +227,7 @@ static std::string letters_in_order(const std::string& order, const std::set<cha
 static int pad_kappa(int64_t K) { return K <= 16 ? 16 : K <= 32 ? 32 : K <= 64 ? 64 : -1; }
 
 Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>& ws_sizes,
-                   std::string& err) {
+                   std::string& err, bool direct_only) {
   const int L = (int)m.ops.size();
   const int M = (int)m.out.size();
   auto obs_of = [&](int o) {
@@ -448,6 +448,7 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
       const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nqo *
                           std::ceil((double)bp2.nqi / qstep) * qstep;
       const double cost = Neff * 6.0 * KP + 16.0 * macs + 8.0 * mat_elems;
+      if (direct_only && (!bp2.L_direct || !kr)) continue;
       if (best_cost < 0 || cost < best_cost) {
         best_cost = cost;
         best = bp2;
@@ -457,7 +458,8 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
   }
   if (best_cost < 0) {
     err = "block " + std::to_string(ell) + " ('" + m.ops[ell] +
-          "') has no lowering with a contraction width <= 64";
+          (direct_only ? "') has no lowering without side operands with a contraction width <= 64"
+                       : "') has no lowering with a contraction width <= 64");
     return ST_UNSUPPORTED;
   }
   bp = best;

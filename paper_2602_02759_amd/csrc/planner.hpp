@@ -93,7 +93,7 @@ struct BlockPlan {
 Status parse_model(const std::string& s, Model& m, std::string& err);
 Status make_loss(double alpha, double beta, LossSpec& ls, std::string& err);
 Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>& ws_sizes,
-                   std::string& err);
+                   std::string& err, bool direct_only = false);
 std::vector<Step> plan_contraction(const Model& m, std::vector<TensorRef> in, const TensorRef& out,
                                    std::vector<int64_t>& ws_sizes, int64_t& macs);
 std::vector<int64_t> row_major_strides(const Model& m, const std::string& subs, int64_t inner);

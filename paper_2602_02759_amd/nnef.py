@@ -34,6 +34,13 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int * 6)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("model_str", ctypes.c_char_p), ("mode_sizes", ctypes.POINTER(ctypes.c_int64)),
+                ("n_modes", ctypes.c_int), ("ranks", ctypes.POINTER(ctypes.c_int64)),
+                ("n_ranks", ctypes.c_int), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("n_restarts", ctypes.c_int), ("masked", ctypes.c_int)]
+
+
 EXPORTS = {
     "nnef_default_options": (None, [ctypes.POINTER(Options)]),
     "nnef_plan": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
@@ -57,6 +64,17 @@ EXPORTS = {
     "nnef_plan_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double)]),
     "nnef_last_error": (ctypes.c_char_p, []),
+    "nnef_batch_plan": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Options),
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "nnef_batch_destroy": (None, [ctypes.c_void_p]),
+    "nnef_batch_num_runs": (ctypes.c_int, [ctypes.c_void_p]),
+    "nnef_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "nnef_batch_describe": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
     "nnef_mlp_num_params": (ctypes.c_int, []),
     "nnef_mlp_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "nnef_mlp_destroy": (None, [ctypes.c_void_p]),
@@ -251,6 +269,95 @@ def nnef_step_learned(h, mlp, Y, M, factors, n_sweeps, propose_every, loss_trace
                                    _factor_array(factors), int(n_sweeps), int(propose_every),
                                    _ptr(loss_trace, torch.float64, "loss_trace"),
                                    _ptr(n_accepted, torch.int32, "n_accepted"), _stream(stream)))
+
+
+def _ptr_array(ts, dtype, what, allow_none=False):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        if t is None and allow_none:
+            arr[i] = None
+        else:
+            arr[i] = _ptr(t, dtype, f"{what} {i}")
+    return arr
+
+
+def nnef_batch_plan(problems, eps=1e-10, prec="fp32"):
+    """problems: list of dicts with model_str, mode_sizes, ranks, alpha, beta,
+    n_restarts and masked."""
+    opt = Options()
+    lib().nnef_default_options(ctypes.byref(opt))
+    opt.eps = eps
+    opt.prec = PREC[prec]
+    arr = (Problem * len(problems))()
+    keep = []
+    for i, d in enumerate(problems):
+        ms = (ctypes.c_int64 * len(d["mode_sizes"]))(*d["mode_sizes"])
+        rk = (ctypes.c_int64 * max(1, len(d["ranks"])))(*d["ranks"])
+        name = d["model_str"].encode()
+        keep += [ms, rk, name]
+        arr[i] = Problem(name, ms, len(d["mode_sizes"]), rk, len(d["ranks"]), float(d["alpha"]),
+                         float(d["beta"]), int(d.get("n_restarts", 1)), int(bool(d.get("masked", 0))))
+    h = ctypes.c_void_p()
+    _check(lib().nnef_batch_plan(arr, len(problems), ctypes.byref(opt), ctypes.byref(h)))
+    return h
+
+
+def _batch_args(Ys, Ms, factors):
+    import torch
+    y = _ptr_array(Ys, torch.float32, "Y")
+    m = _ptr_array(Ms, torch.uint8, "mask", allow_none=True) if Ms is not None else None
+    flat = [f for run in factors for f in run]
+    return y, m, _factor_array(flat)
+
+
+def nnef_batch_step(h, Ys, Ms, factors, n_sweeps, loss_trace=None, stream=None):
+    import torch
+    y, m, f = _batch_args(Ys, Ms, factors)
+    _check(lib().nnef_batch_step(h, y, m, f, int(n_sweeps), _ptr(loss_trace, torch.float64, "loss_trace"),
+                                 _stream(stream)))
+
+
+def nnef_batch_autotune(h, Ys, Ms, factors, stream=None):
+    y, m, f = _batch_args(Ys, Ms, factors)
+    _check(lib().nnef_batch_autotune(h, y, m, f, _stream(stream)))
+
+
+def nnef_batch_describe(h):
+    n = lib().nnef_batch_describe(h, None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().nnef_batch_describe(h, buf, n + 1)
+    return buf.value.decode()
+
+
+class Batch:
+    """Owner of an ``nnef_batch_t``: many problems x restarts swept together.
+    ``factors`` arguments are lists (one per run, problem-major) of factor lists."""
+
+    def __init__(self, problems, eps=1e-10, prec="fp32"):
+        self.h = nnef_batch_plan(problems, eps, prec)
+        self.n_runs = lib().nnef_batch_num_runs(self.h)
+
+    def step(self, Ys, Ms, factors, n_sweeps=1, loss_trace=None, stream=None):
+        if len(factors) != self.n_runs:
+            raise ValueError(f"expected {self.n_runs} runs, got {len(factors)}")
+        nnef_batch_step(self.h, Ys, Ms, factors, n_sweeps, loss_trace, stream)
+
+    def autotune(self, Ys, Ms, factors, stream=None):
+        nnef_batch_autotune(self.h, Ys, Ms, factors, stream)
+
+    def describe(self):
+        return nnef_batch_describe(self.h)
+
+    def close(self):
+        if self.h:
+            lib().nnef_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Mlp:
