@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--beta", type=float, default=1.0)
+    ap.add_argument("--workload", choices=("cp", "batched", "tucker", "tt"), default="cp",
+                    help="cp: the CP 256^3 headline; batched: 96 CP4 problems x 8 restarts; "
+                         "tucker / tt: the Tucker IS and tensor-train workloads")
     ap.add_argument("--n", type=int, default=256, help="mode size")
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--prec", choices=("fp32", "bf16", "fp16"), default="fp32",
@@ -91,16 +94,26 @@ def load_target(alpha, beta):
     return None if t is None else t["L_star"]
 
 
-def run_to_target(phases, Y, M, init, target, chunk, max_sweeps):
+def run_to_target(phases, Y, M, init, target, chunk, max_sweeps, graph=False):
     """Sweeps from ``init`` until the loss (FP32 terms, FP64 sums, taken at the
     start of every sweep inside the fused pass) is <= target.  ``phases`` is a
     list of (name, run) with run(Y, M, factors, n_sweeps, loss_trace); a phase
     ends when the target is met or its loss stalls (relative decrease over a
-    chunk < 1e-6), then the next one starts.  Returns the host wall time,
-    including every sync and loss read-back."""
+    chunk < 1e-6), then the next one starts.  With ``graph``, each phase's
+    chunk of sweeps is captured once in a graph (before the clock starts) and
+    replayed.  Returns the host wall time, including every sync and loss
+    read-back."""
     import torch
     f = [t.clone() for t in init]
     tr = torch.empty(chunk, dtype=torch.float64, device=Y.device)
+    if graph:
+        graphs = []
+        for name, run in phases:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                run(Y, M, f, chunk, tr)
+            graphs.append(g)
+        phases = [(name, (lambda g: (lambda *a: g.replay()))(g)) for (name, _), g in zip(phases, graphs)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done, hit, per_phase, last = 0, None, {}, None
@@ -193,12 +206,110 @@ def train_extrapolator(n_sweeps=200):
     return mlp, info
 
 
+def bench_batched(args):
+    """96 CP 'ir,jr,kr,lr->ijkl' problems (mode sizes uniform in [32, 160],
+    ranks in {4, 8, 16, 32, 64}) x 8 restarts, KL, no mask, in one batched plan:
+    autotuned tiling, graph-replayed sweeps.  Data are drawn on the GPU from a
+    seeded generator (Gamma(0.5, 1) factors, Poisson counts)."""
+    import torch
+
+    from paper_2602_02759_amd import datagen
+    from paper_2602_02759_amd.nnef import Batch
+    desc = datagen.cp4_batch_descriptors()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    t0 = time.perf_counter()
+    Ys, runs, problems, N_tot, flops = [], [], [], 0, 0.0
+    for dims, R in desc:
+        fs = [torch._standard_gamma(torch.full((d, R), 0.5, device="cuda"), generator=gen) for d in dims]
+        lam = torch.einsum("ir,jr,kr,lr->ijkl", *fs).contiguous()
+        Ys.append(torch.poisson(lam, generator=gen).contiguous())
+        del lam, fs
+        for _ in range(8):
+            runs.append([torch._standard_gamma(torch.ones((d, R), device="cuda"), generator=gen).clamp_min(1e-10)
+                         for d in dims])
+        problems.append(dict(model_str="ir,jr,kr,lr->ijkl", mode_sizes=dims, ranks=[R], alpha=1.0,
+                             beta=0.0, n_restarts=8, masked=False))
+        N = dims[0] * dims[1] * dims[2] * dims[3]
+        N_tot += N
+        flops += 8 * 4 * 4.0 * R * N  # 8 restarts, 4 blocks, 4R flops per entry (D in closed form)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    b = Batch(problems)
+    t1 = time.perf_counter()
+    b.autotune(Ys, None, runs)
+    t_tune = time.perf_counter() - t1
+    b.step(Ys, None, runs, n_sweeps=max(1, args.warmup))  # builds tables, captures the graph
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    b.step(Ys, None, runs, n_sweeps=args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    tf = flops / (ms / 1e3) / 1e12
+    gbs = 4 * 4.0 * N_tot / (ms / 1e3) / 1e9  # Y read once per block for each problem
+    out = {"metric": "batched MU sweeps/s (96 CP4 problems x 8 restarts, one sweep of all 768 runs)",
+           "value": 1e3 / ms, "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "96 CP 'ir,jr,kr,lr->ijkl' problems, mode sizes U{32..160}, ranks "
+                                  "{4,8,16,32,64}, 8 restarts each, Poisson(Gamma(0.5,1) CP), KL, no mask",
+                      "entries_total": N_tot, "runs": len(runs)},
+           "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                        "frac": tf / PEAK["fp32"], "traffic": None,
+                        "alg_flops_per_sweep": flops, "alg_GBps_Y_once_per_problem": gbs},
+           "autotune": b.describe().splitlines()[-3:], "gen_s": t_gen, "autotune_s": t_tune}
+    print(json.dumps(out), flush=True)
+
+
+def bench_single(args):
+    """The Tucker 512x512x128 IS workload or the tensor-train 128x128x96x64 KL
+    workload: plain FP32 and BF16-contraction sweeps/s."""
+    import numpy as np
+    import torch
+
+    from paper_2602_02759_amd import datagen
+    from paper_2602_02759_amd.nnef import Plan
+    p = datagen.tucker3() if args.workload == "tucker" else datagen.tt4()
+    Y = torch.from_numpy(p.Y).cuda()
+    M = torch.from_numpy(p.M).cuda() if p.M is not None else None
+    res = {}
+    for prec in ("fp32", "bf16"):
+        plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, prec=prec)
+        f = [torch.from_numpy(np.maximum(t, 1e-10)).cuda() for t in p.init]
+        plan.step(Y, M, f, n_sweeps=args.warmup)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        plan.step(Y, M, f, n_sweeps=args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        n_pass, pass_ms = plan.timing()
+        plan.set_timing(False)
+        res[prec] = {"sweeps_per_s": 1e3 * args.steps / ev0.elapsed_time(ev1),
+                     "avg_fused_pass_us": 1e3 * pass_ms / max(n_pass, 1), "lowering": plan.describe()}
+    out = {"metric": f"MU sweeps/s ({p.name})", "value": res["fp32"]["sweeps_per_s"], "unit": "sweeps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 / res["fp32"]["sweeps_per_s"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{p.model_str} sizes {p.sizes} (alpha,beta)=({p.alpha},{p.beta})"},
+           "by_precision": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the method's multi-GPU sharding is described, not built).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload in ("tucker", "tt"):
+        return bench_single(args)
     import numpy as np
     import torch
 
@@ -294,6 +405,13 @@ def main():
         if info is not None:
             res["bf16_learned"]["proposals_accepted"] = int(acc16.item() + acc32.item())
             res["bf16_learned"]["propose_every"] = PROPOSE_EVERY
+            acc16.zero_()
+            acc32.zero_()
+            # the same arm with each chunk of sweeps replayed from a captured graph
+            res["bf16_learned_graph"] = run_to_target(arms["bf16_learned"], Y, M, init, thr, 10, 1000,
+                                                      graph=True)
+            res["bf16_learned_graph"]["proposals_accepted"] = int(acc16.item() + acc32.item())
+            res["bf16_learned_graph"]["propose_every"] = PROPOSE_EVERY
         base = res["plain_fp32"]
         out["time_to_target"] = {
             "L_star": target, "threshold": thr,
