@@ -180,6 +180,66 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
   a.out[ooff] = (float)acc;
 }
 
+// The same contraction with G lanes per output (G a power of two <= 64): lane
+// g of an output's group sums the flattened summed indices c = g, g + G, ...,
+// four at a time so that several loads are in flight, and the group adds its
+// lanes' sums with a fixed butterfly (deterministic).  Used when there are
+// few outputs with long sums, where one thread per output leaves the chip
+// idle and every thread waits on one load per term.
+template <int NIN>
+__global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log2g, uint32_t n_sum) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int G = 1 << log2g;
+  const int64_t o = t >> log2g;
+  const uint32_t g = (uint32_t)(t & (G - 1));
+  const bool valid = o < a.n_out_total;
+  int64_t off[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) off[i] = 0;
+  int64_t ooff = 0;
+  if (valid) {
+    int64_t rem = o;
+    for (int d = a.n_out - 1; d >= 0; --d) {
+      const int64_t v = rem % a.out_size[d];
+      rem /= a.out_size[d];
+      ooff += v * a.out_stride[d];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) off[i] += v * a.in_out_stride[i][d];
+    }
+  }
+  double acc = 0.0;
+  if (valid) {
+    for (uint32_t c0 = g; c0 < n_sum; c0 += 4u * (uint32_t)G) {
+      float prod[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t c = c0 + (uint32_t)u * (uint32_t)G;
+        prod[u] = 0.f;
+        if (c < n_sum) {
+          int64_t so[NIN];
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) so[i] = off[i];
+          uint32_t rem = c;
+          for (int d = a.n_sum - 1; d >= 0; --d) {
+            const uint32_t sz = (uint32_t)a.sum_size[d];
+            const uint32_t v = rem % sz;
+            rem /= sz;
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) so[i] += (int64_t)v * a.in_sum_stride[i][d];
+          }
+          float pr = 1.f;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) pr *= a.in[i][so[i]];
+          prod[u] = pr;
+        }
+      }
+      acc += ((double)prod[0] + (double)prod[1]) + ((double)prod[2] + (double)prod[3]);
+    }
+  }
+  for (int m = G >> 1; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if (valid && g == 0) a.out[ooff] = (float)acc;
+}
+
 // Missing entries become -1 (observed data are nonnegative); the value stored
 // at a missing entry is never read into arithmetic, only replaced.
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Y,
@@ -258,6 +318,24 @@ int launch_update_batched(const UpdateArgs* args, const int* colsum_runs, int n_
 
 int launch_einsum(const EinsumArgs& a, void* stream) {
   if (a.n_out_total <= 0) return 0;
+  int64_t n_sum = 1;
+  for (int d = 0; d < a.n_sum; ++d) n_sum *= a.sum_size[d];
+  if (n_sum >= 16 && n_sum < (int64_t(1) << 31) && a.n_in >= 1 && a.n_in <= 4) {
+    // lanes per output: enough threads to fill the chip, at most 64
+    int log2g = 0;
+    while (log2g < 6 && (a.n_out_total << log2g) < (int64_t(1) << 19) && (int64_t(4) << log2g) < n_sum)
+      ++log2g;
+    const int64_t threads = a.n_out_total << log2g;
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    hipStream_t s = (hipStream_t)stream;
+    switch (a.n_in) {
+      case 1: hipLaunchKernelGGL(einsum_split_kernel<1>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
+      case 2: hipLaunchKernelGGL(einsum_split_kernel<2>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
+      case 3: hipLaunchKernelGGL(einsum_split_kernel<3>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
+      default: hipLaunchKernelGGL(einsum_split_kernel<4>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
+    }
+    return (int)hipGetLastError();
+  }
   const int64_t grid = (a.n_out_total + 255) / 256;
   hipLaunchKernelGGL(einsum_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
