@@ -354,17 +354,32 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
 }
 
 // Fixed-order sum of the gradient partials; optional Adam step on the FP32
-// master parameters (m, v: FP32 moments; bc1, bc2: bias corrections).
+// master parameters (m, v: FP32 moments; bc1, bc2: bias corrections).  One
+// workgroup per 64 parameters: wave w sums partials w, w + 4, ... with eight
+// independent accumulators (eight loads in flight), then wave 0 adds the four
+// wave sums in a fixed order.
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* gpart, const double* lpart,
                                                          int grid, float inv_n, float* grad_out,
                                                          double* loss_out, float* params, float* m,
                                                          float* v, float lr, float b1, float b2,
                                                          float eps, float bc1, float bc2, int adam) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k < kMlpParams) {
-    double s = 0.0;
-    for (int w = 0; w < grid; ++w) s += (double)gpart[(int64_t)w * kMlpParams + k];
-    const float gk = (float)s;
+  __shared__ double sw[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  const bool valid = k < kMlpParams;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (valid) {
+    int r = w;
+    for (; r + 28 < grid; r += 32) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] += (double)gpart[(int64_t)(r + 4 * j) * kMlpParams + k];
+    }
+    for (; r < grid; r += 4) acc[0] += (double)gpart[(int64_t)r * kMlpParams + k];
+  }
+  sw[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (w == 0 && valid) {
+    const float gk = (float)(((sw[0][lane] + sw[1][lane]) + sw[2][lane]) + sw[3][lane]);
     if (grad_out) grad_out[k] = gk;
     if (adam) {
       const float mk = b1 * m[k] + (1.f - b1) * gk;
@@ -374,10 +389,12 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* gpart, con
       params[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
+  if (blockIdx.x == 0 && w == 1 && loss_out) {
     double l = 0.0;
-    for (int w = 0; w < grid; ++w) l += lpart[w];
-    *loss_out = l * (double)inv_n;
+    for (int i = lane; i < grid; i += 64) l += lpart[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+    if (lane == 0) *loss_out = l * (double)inv_n;
   }
 }
 
@@ -458,7 +475,7 @@ int launch_mlp(const MlpArgs& a, int mode, int grid, void* stream) {
 int launch_mlp_reduce(const float* gpart, const double* lpart, int grid, float inv_n, float* grad_out,
                       double* loss_out, float* params, float* m, float* v, float lr, float b1, float b2,
                       float eps, float bc1, float bc2, int adam, void* stream) {
-  mlp_reduce_kernel<<<grid_of(kMlpParams), 256, 0, (hipStream_t)stream>>>(
+  mlp_reduce_kernel<<<(kMlpParams + 63) / 64, 256, 0, (hipStream_t)stream>>>(
       gpart, lpart, grid, inv_n, grad_out, loss_out, params, m, v, lr, b1, b2, eps, bc1, bc2, adam);
   return (int)hipGetLastError();
 }
