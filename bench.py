@@ -291,12 +291,38 @@ def bench_single(args):
         plan.set_timing(False)
         res[prec] = {"sweeps_per_s": 1e3 * args.steps / ev0.elapsed_time(ev1),
                      "avg_fused_pass_us": 1e3 * pass_ms / max(n_pass, 1), "lowering": plan.describe()}
+    # time to the plain FP32 run's own loss after 200 sweeps, for the plain,
+    # BF16 and learned forms (the extrapolator is trained on NMF, CP and Tucker
+    # trajectories drawn with other seeds)
+    ttt = None
+    if not args.no_target:
+        init = [torch.from_numpy(np.maximum(t, 1e-10)).cuda() for t in p.init]
+        plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta)
+        plan16 = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, prec="bf16")
+        f = [t.clone() for t in init]
+        tr = torch.zeros(201, dtype=torch.float64, device="cuda")
+        plan.step(Y, M, f, n_sweeps=200, loss_trace=tr[:200])
+        plan.loss_device(Y, M, f, tr[200:])
+        target = tr[200].item()
+        thr = target * (1 + 1e-4)
+        arms = {"plain_fp32": [("fp32", plain(plan))], "bf16": [("bf16", plain(plan16)), ("fp32", plain(plan))]}
+        mlp, info = train_extrapolator()
+        acc = torch.zeros(1, dtype=torch.int32, device="cuda")
+        arms["bf16_learned"] = [("bf16", with_proposals(plan16, mlp, PROPOSE_EVERY, acc)),
+                                ("fp32", with_proposals(plan, mlp, PROPOSE_EVERY, acc))]
+        ttt = {k: run_to_target(v, Y, M, init, thr, 10, 600) for k, v in arms.items()}
+        ttt["bf16_learned"]["proposals_accepted"] = int(acc.item())
+        base = ttt["plain_fp32"]
+        ttt = {"target": "loss of 200 plain FP32 sweeps on the GPU, x (1 + 1e-4)", "L_200": target, **ttt,
+               "speedup": {k: (base["wall_s"] / r["wall_s"] if base["reached"] and r["reached"] else None)
+                           for k, r in ttt.items() if k != "plain_fp32"},
+               "note": "BF16 applies to width-32 blocks only" }
     out = {"metric": f"MU sweeps/s ({p.name})", "value": res["fp32"]["sweeps_per_s"], "unit": "sweeps/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 / res["fp32"]["sweeps_per_s"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{p.model_str} sizes {p.sizes} (alpha,beta)=({p.alpha},{p.beta})"},
-           "by_precision": res}
+           "by_precision": res, "time_to_target": ttt}
     print(json.dumps(out), flush=True)
 
 
