@@ -165,11 +165,71 @@ def _xlogx_ratio(coef, x, y):
     return np.where(coef == 0, 0.0, v)
 
 
+# --------------------------------------------------------------------------
+# Other decomposable likelihoods (App. B, after the (alpha, beta) family):
+# negative binomial with dispersion phi, binomial odds with n trials (n = 1:
+# Bernoulli), and Jensen-Shannon.  Passed in place of (alpha, beta) as
+# ``alpha=<Family>``; every function below dispatches on it.
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Family:
+    kind: str           # "negbin" | "binomial" | "js"
+    param: float = 0.0  # phi (negbin) or n (binomial)
+
+
+def negbin(phi: float) -> Family:
+    return Family("negbin", float(phi))
+
+
+def binomial(n: float = 1.0) -> Family:
+    return Family("binomial", float(n))
+
+
+def jensen_shannon() -> Family:
+    return Family("js")
+
+
+def _xlogx(x):
+    x = np.asarray(x, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(x > 0, x * np.log(np.where(x > 0, x, 1.0)), 0.0)
+
+
+def family_loss(x, y, fam: Family):
+    """The negative log-likelihood terms (or divergence) the paper gives for
+    each family, x the data and y the model (the odds for the binomial)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        if fam.kind == "negbin":    # (phi + x) log(phi + y) - x log y
+            return (fam.param + x) * np.log(fam.param + y) - np.where(x > 0, x * np.log(y), 0.0)
+        if fam.kind == "binomial":  # n log(1 + y) - x log y
+            return fam.param * np.log1p(y) - np.where(x > 0, x * np.log(y), 0.0)
+        if fam.kind == "js":        # (x log x + y log y)/2 - ((x+y)/2) log((x+y)/2)
+            return 0.5 * (_xlogx(x) + _xlogx(y)) - _xlogx(0.5 * (x + y))
+    raise ValueError(fam.kind)
+
+
+def family_weights(x, y, fam: Family):
+    """(a, b) of each family's convex-concave split."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if fam.kind == "negbin":
+        return x / y, (fam.param + x) / (fam.param + y)
+    if fam.kind == "binomial":
+        return x / y, fam.param / (1.0 + y)
+    if fam.kind == "js":
+        return np.log((x + y) / (2.0 * y)), np.ones_like(y)
+    raise ValueError(fam.kind)
+
+
 def ab_loss(x, y, alpha: float, beta: float):
     """Elementwise D_{alpha,beta}(x, y): x is the data, y the model (App. B).
 
     The five cases of the definition, in its order.
     """
+    if isinstance(alpha, Family):
+        return family_loss(x, y, alpha)
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     a, b = float(alpha), float(beta)
@@ -197,6 +257,8 @@ def ab_weights(x, y, alpha: float, beta: float):
     alpha == 0, beta == 1: a = log(x / y), b = 1.
     alpha == 0, beta != 1: no decomposition is known -> ValueError.
     """
+    if isinstance(alpha, Family):
+        return family_weights(x, y, alpha)
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     if alpha != 0:
@@ -213,7 +275,10 @@ def update_rule(alpha: float, beta: float):
     From the four cases of g(lambda) in App. B with rho = (1 - beta)/alpha:
     rho > 1: g = lambda^(1-beta); rho < 0: g = lambda^(alpha+beta-1);
     0 <= rho <= 1: g = lambda^alpha; alpha = 0, beta = 1: g = log.
+    Other families: g = lambda (negative binomial, binomial), g = log (JS).
     """
+    if isinstance(alpha, Family):
+        return ("exp", None) if alpha.kind == "js" else ("pow", 1.0)
     if alpha == 0:
         if beta == 1:
             return ("exp", None)
