@@ -67,11 +67,27 @@ typedef enum {
  * nnef_plan_describe reports the precision chosen for every block. */
 typedef enum { NNEF_FP32 = 0, NNEF_BF16 = 1, NNEF_FP16 = 2 } nnef_prec;
 
+/* Likelihood family.  NNEF_AB: the (alpha, beta)-divergence (App. B), with
+ * the alpha, beta passed to nnef_plan.  The other decomposable likelihoods of
+ * App. B ignore alpha and beta:
+ *   NNEF_NEGBIN   negative binomial with dispersion phi = family_param > 0:
+ *                 a = y/yhat, b = (phi + y)/(phi + yhat), update exponent 1;
+ *                 loss (phi + y) log(phi + yhat) - y log yhat.
+ *   NNEF_BINOMIAL binomial odds with n = family_param > 0 trials (n = 1:
+ *                 Bernoulli), yhat the odds: a = y/yhat, b = n/(1 + yhat),
+ *                 exponent 1; loss n log(1 + yhat) - y log yhat.
+ *   NNEF_JS       Jensen-Shannon: a = log((y + yhat)/(2 yhat)), b = 1,
+ *                 exponential update; loss (y log y + yhat log yhat)/2
+ *                 - m log m, m = (y + yhat)/2.                               */
+typedef enum { NNEF_AB = 0, NNEF_NEGBIN = 1, NNEF_BINOMIAL = 2, NNEF_JS = 3 } nnef_family;
+
 typedef struct {
   double eps;          /* floor of eq. 3.1; default 1e-10                        */
   int    prec;         /* nnef_prec; default NNEF_FP32                           */
   int    deterministic;/* 1 (default): fixed-order reductions, bitwise repeatable */
-  int    reserved[6];  /* must be zero                                           */
+  int    family;       /* nnef_family; default NNEF_AB                           */
+  int    reserved[5];  /* must be zero                                           */
+  double family_param; /* phi (NNEF_NEGBIN) or n (NNEF_BINOMIAL)                 */
 } nnef_options;
 
 /* Fill *opt with the defaults. */

@@ -144,6 +144,10 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
       free_plan(p);
       return fail(NNEF_E_ARG, "prec must be NNEF_FP32, NNEF_BF16 or NNEF_FP16");
     }
+    if (p->opt.family < NNEF_AB || p->opt.family > NNEF_JS) {
+      free_plan(p);
+      return fail(NNEF_E_ARG, "family must be one of NNEF_AB, NNEF_NEGBIN, NNEF_BINOMIAL, NNEF_JS");
+    }
   }
   std::string err;
   if (parse_model(model_str, p->m, err) != ST_OK) {
@@ -179,7 +183,8 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
     m.size[(unsigned char)m.latent[i]] = ranks[i];
   }
   p->n_data = N;
-  if (make_loss(alpha, beta, p->ls, err) != ST_OK) {
+  if ((p->opt.family == NNEF_AB ? make_loss(alpha, beta, p->ls, err)
+                                : make_family(p->opt.family, p->opt.family_param, p->ls, err)) != ST_OK) {
     free_plan(p);
     return fail(NNEF_E_LOSS_UNSUPPORTED, err);
   }
@@ -386,6 +391,7 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.ab_inv = ab != 0 ? (float)(1.0 / ab) : 0.f;
   a.apb_inv = apb != 0 ? (float)(1.0 / apb) : 0.f;
   a.lk = p->ls.lk;
+  a.fparam = (float)p->ls.fparam;
   a.prec = (bp.KP == 32 && bp.qstep == 32) ? p->opt.prec : 0;
   a.full = (bp.K == bp.KP && bp.nqi % bp.qstep == 0 && bp.nP % bp.rows == 0 && bp.in_stride == 1 &&
             bp.pieces[bp.inner].ld == bp.KP) ? 1 : 0;

@@ -82,9 +82,18 @@ __device__ __forceinline__ void ab_weights(float y, float yh, float al, float be
     float ly = fast_log2(yh);
     wb = fast_exp2((al + be - 1.f) * ly);
     wa = powpos(y, al) * fast_exp2((be - 1.f) * ly);
-  } else {  // WK_RKL
+  } else if constexpr (WK == WK_RKL) {
     wa = fast_log2(y * fast_rcp(yh)) * 0.69314718055994531f;
     wb = 1.f;
+  } else {  // WK_FAM: al carries the family parameter, be the LossKind
+    const int lk = (int)be;
+    if (lk == LK_JS) {
+      wa = fast_log2((y + yh) * 0.5f * fast_rcp(yh)) * 0.69314718055994531f;
+      wb = 1.f;
+    } else {
+      wa = y * fast_rcp(yh);
+      wb = lk == LK_NB ? (al + y) * fast_rcp(al + yh) : al * fast_rcp(1.f + yh);
+    }
   }
 }
 
@@ -137,6 +146,17 @@ __device__ __forceinline__ float ab_loss(float y, float yh, const FusedArgs& a) 
     return (2.f / 3.f) * d * d * (sy + 2.f * v);
   } else if constexpr (WK == WK_RKL) {  // (0, 1): yh log(yh/y) - yh + y
     return y > 0.f ? y * xlogx_m(yh / y - 1.f) : INFINITY;
+  } else if constexpr (WK == WK_FAM) {
+    const float ph = a.fparam;
+    if (a.lk == LK_NB)  // (phi + y) log(phi + yh) - y log yh
+      return ((ph + y) * fast_log2(ph + yh) - (y > 0.f ? y * fast_log2(yh) : 0.f)) * ln2;
+    if (a.lk == LK_BIN)  // n log(1 + yh) - y log yh
+      return ph * log1pf(yh) - (y > 0.f ? y * fast_log2(yh) * ln2 : 0.f);
+    // Jensen-Shannon: (y log y + yh log yh)/2 - m log m, m = (y + yh)/2, written as
+    // (y log(y/m) + yh log(yh/m))/2
+    const float m = 0.5f * (y + yh);
+    const float ty = y > 0.f ? y * fast_log2(y / m) : 0.f;
+    return 0.5f * (ty + yh * fast_log2(yh / m)) * ln2;
   } else {
     const float al = a.alpha, be = a.beta;
     if (a.lk == LK_GENERIC)
@@ -178,7 +198,7 @@ struct Tile {
 // yhat >= FLT_MIN (exact arithmetic keeps yhat > 0; FP32 may underflow).
 template <int WK>
 __device__ constexpr bool needs_floor() {
-  return WK == WK_KL || WK == WK_IS || WK == WK_GEN || WK == WK_RKL;
+  return WK == WK_KL || WK == WK_IS || WK == WK_GEN || WK == WK_RKL || WK == WK_FAM;
 }
 
 // Weight kinds whose a(y, yhat) vanishes at y = 0 (alpha > 0), so a missing
@@ -423,12 +443,15 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float yv = ym.y[t][r];
-      const bool obs = !masked || yv >= 0.f;
-      const float y = masked ? fmaxf(yv, 0.f) : yv;
+      // ragged tiles pad out-of-range entries with -1 as well: they count as
+      // missing whether or not the caller passed a mask
+      const bool obs = (FULL && !masked) || yv >= 0.f;
+      const float y = (masked || !FULL) ? fmaxf(yv, 0.f) : yv;
       const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[r], FLT_MIN, FLT_MAX) : yh[r];
       if constexpr (ND) {
         float xa, xb;
-        ab_weights<WK>(y, yhat, a.alpha, a.beta, xa, xb);
+        ab_weights<WK>(y, yhat, WK == WK_FAM ? a.fparam : a.alpha, WK == WK_FAM ? (float)a.lk : a.beta,
+                       xa, xb);
         wa[r] = obs ? xa : 0.f;
         wb[r] = obs ? xb : 0.f;
       }
@@ -607,7 +630,8 @@ int launch_fused_w(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t 
     case WK_SQRT: return launch_fused_v<KP, WK_SQRT>(a, vecq, mode, s);
     case WK_IS: return launch_fused_v<KP, WK_IS>(a, vecq, mode, s);
     case WK_GEN: return launch_fused_v<KP, WK_GEN>(a, vecq, mode, s);
-    default: return launch_fused_v<KP, WK_RKL>(a, vecq, mode, s);
+    case WK_RKL: return launch_fused_v<KP, WK_RKL>(a, vecq, mode, s);
+    default: return launch_fused_v<KP, WK_FAM>(a, vecq, mode, s);
   }
 }
 
@@ -638,7 +662,8 @@ int launch_fused_batched_w(const BatchedLaunch& L, hipStream_t s) {
     case WK_SQRT: return launch_fused_batched_v<KP, WK_SQRT>(L, s);
     case WK_IS: return launch_fused_batched_v<KP, WK_IS>(L, s);
     case WK_GEN: return launch_fused_batched_v<KP, WK_GEN>(L, s);
-    default: return launch_fused_batched_v<KP, WK_RKL>(L, s);
+    case WK_RKL: return launch_fused_batched_v<KP, WK_RKL>(L, s);
+    default: return launch_fused_batched_v<KP, WK_FAM>(L, s);
   }
 }
 

@@ -235,13 +235,16 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float yv = ym.y[v >> 2][v & 3];
-      const bool obs = !masked || yv >= 0.f;
+      // ragged tiles pad out-of-range entries with -1 as well: they count as
+      // missing whether or not the caller passed a mask
+      const bool obs = (FULL && !masked) || yv >= 0.f;
       // a missing entry (-1) becomes 0: a(0, yhat) = 0 for alpha > 0
-      const float y = masked ? __builtin_amdgcn_fmed3f(yv, 0.f, FLT_MAX) : yv;
+      const float y = (masked || !FULL) ? __builtin_amdgcn_fmed3f(yv, 0.f, FLT_MAX) : yv;
       const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[v], FLT_MIN, FLT_MAX) : yh[v];
       if constexpr (ND) {
         float xa, xb;
-        ab_weights<WK>(y, yhat, a.alpha, a.beta, xa, xb);
+        ab_weights<WK>(y, yhat, WK == WK_FAM ? a.fparam : a.alpha, WK == WK_FAM ? (float)a.lk : a.beta,
+                       xa, xb);
         wa[v] = (a_zero_at_zero<WK>() || obs) ? xa : 0.f;
         wb[v] = obs ? xb : 0.f;
       }
@@ -499,7 +502,8 @@ int launch_x32(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
     case WK_SQRT: return launch_x32_w<WK_SQRT>(a, vecq, mode, s);
     case WK_IS: return launch_x32_w<WK_IS>(a, vecq, mode, s);
     case WK_GEN: return launch_x32_w<WK_GEN>(a, vecq, mode, s);
-    default: return launch_x32_w<WK_RKL>(a, vecq, mode, s);
+    case WK_RKL: return launch_x32_w<WK_RKL>(a, vecq, mode, s);
+    default: return launch_x32_w<WK_FAM>(a, vecq, mode, s);
   }
 }
 
@@ -536,7 +540,8 @@ int launch_x32_batched(const BatchedLaunch& L, hipStream_t s) {
     case WK_SQRT: return launch_x32_batched_w<WK_SQRT>(L, s);
     case WK_IS: return launch_x32_batched_w<WK_IS>(L, s);
     case WK_GEN: return launch_x32_batched_w<WK_GEN>(L, s);
-    default: return launch_x32_batched_w<WK_RKL>(L, s);
+    case WK_RKL: return launch_x32_batched_w<WK_RKL>(L, s);
+    default: return launch_x32_batched_w<WK_FAM>(L, s);
   }
 }
 

@@ -18,7 +18,9 @@ enum WeightKind : int {
   WK_IS = 3,    // (1, -1):  a = y/yh^2,            b = 1/yh
   WK_GEN = 4,   // alpha!=0: a = y^al yh^(be-1),    b = yh^(al+be-1)
   WK_RKL = 5,   // (0, 1):   a = log(y/yh),         b = 1
-  WK_COUNT = 6
+  WK_FAM = 6,   // other families (LossKind selects): negative binomial,
+                // binomial odds, Jensen-Shannon
+  WK_COUNT = 7
 };
 
 // g^{-1} of App. B: r^gamma with the exponent specialised, or exp(r).
@@ -27,13 +29,15 @@ enum UpdateKind : int { UP_ONE = 0, UP_SQR = 1, UP_SQRT = 2, UP_POW = 3, UP_EXP 
 // Case of the (alpha, beta)-divergence definition (App. B), plus closed forms.
 enum LossKind : int {
   LK_GENERIC = 0, LK_BETA0 = 1, LK_AMB = 2, LK_ALPHA0 = 3, LK_ZERO = 4,
-  LK_KL = 5, LK_EUC = 6, LK_IS = 7, LK_SQRT = 8
+  LK_KL = 5, LK_EUC = 6, LK_IS = 7, LK_SQRT = 8,
+  LK_NB = 9, LK_BIN = 10, LK_JS = 11  // with WK_FAM
 };
 
 struct LossSpec {
   double alpha = 1, beta = 0, gamma = 1;
+  double fparam = 0;           // negative binomial phi, binomial n
   int wk = WK_KL, upd = UP_ONE, lk = LK_KL;
-  bool b_is_one() const { return wk == WK_KL || wk == WK_RKL; }
+  bool b_is_one() const { return wk == WK_KL || wk == WK_RKL || (wk == WK_FAM && lk == LK_JS); }
 };
 
 // ---------------------------------------------------------------------------
@@ -81,7 +85,8 @@ struct FusedArgs {
   int no_d;                    // D is a closed form (b = 1, no mask): skip it
   float alpha, beta;           // for WK_GEN and the generic loss
   float ab_inv, apb_inv;       // 1/(alpha*beta), 1/(alpha+beta)
-  int lk;                      // LossKind (generic weights only)
+  int lk;                      // LossKind (generic weights and WK_FAM)
+  float fparam;                // WK_FAM: negative binomial phi, binomial n
   int full;                    // no ragged edges: K = KP, nqi % 16 = 0, nP % rows = 0
   int prec;                    // contraction inputs: 0 FP32, 1 BF16, 2 FP16 (width 32)
 };

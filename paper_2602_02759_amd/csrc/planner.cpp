@@ -27,6 +27,34 @@ namespace nnef {
 
 static bool is_letter(char c) { return (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z'); }
 
+// The other decomposable likelihoods of App. B: negative binomial (phi),
+// binomial odds (n trials; n = 1 is Bernoulli): a = y/yh, g = lambda;
+// Jensen-Shannon: a = log((y + yh)/(2 yh)), b = 1, g = log.
+Status make_family(int family, double param, LossSpec& ls, std::string& err) {
+  ls.alpha = 1.0;
+  ls.beta = 0.0;
+  ls.wk = WK_FAM;
+  ls.gamma = 1.0;
+  ls.fparam = param;
+  if (family == 1 || family == 2) {
+    if (!(param > 0.0) || !std::isfinite(param)) {
+      err = family == 1 ? "the negative binomial dispersion phi must be positive and finite"
+                        : "the number of binomial trials n must be positive and finite";
+      return ST_LOSS;
+    }
+    ls.upd = UP_ONE;
+    ls.lk = family == 1 ? LK_NB : LK_BIN;
+    return ST_OK;
+  }
+  if (family == 3) {
+    ls.upd = UP_EXP;
+    ls.lk = LK_JS;
+    return ST_OK;
+  }
+  err = "unknown likelihood family";
+  return ST_LOSS;
+}
+
 // ---------------------------------------------------------------------------
 // Model strings (Sec. 2, eq. 2.2)
 // ---------------------------------------------------------------------------

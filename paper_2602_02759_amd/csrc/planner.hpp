@@ -92,6 +92,7 @@ struct BlockPlan {
 
 Status parse_model(const std::string& s, Model& m, std::string& err);
 Status make_loss(double alpha, double beta, LossSpec& ls, std::string& err);
+Status make_family(int family, double param, LossSpec& ls, std::string& err);
 Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>& ws_sizes,
                    std::string& err, bool direct_only = false);
 std::vector<Step> plan_contraction(const Model& m, std::vector<TensorRef> in, const TensorRef& out,

@@ -41,6 +41,8 @@ class Problem:
     init: list                       # float32 factors, axes in subscript order
     truth: list = field(default_factory=list)
     n_sweeps: int = 1
+    family: str = "ab"               # "ab" ((alpha, beta) divergence), "negbin", "binomial", "js"
+    family_param: float = 0.0        # negative binomial phi, binomial n
 
     @property
     def operands(self):
@@ -117,6 +119,34 @@ def gamma_noise_problem(name, model_str, sizes, alpha, beta, *, seed,
     M = bernoulli_mask(Y.shape, missing, seed)
     return Problem(name, model_str, dict(sizes), alpha, beta, Y, M,
                    init_factors(model_str, sizes, seed), truth, n_sweeps)
+
+
+def negbin_problem(name, model_str, sizes, phi, *, seed, truth_shape, missing=0.0):
+    """Y ~ NegBinom(mean einsum(model_str, truth), dispersion phi)."""
+    truth = gamma_factors(model_str, sizes, truth_shape, 1.0, rng(seed, STREAM_TRUTH))
+    lam = mean_tensor(model_str, truth)
+    Y = rng(seed, STREAM_NOISE).negative_binomial(phi, phi / (phi + lam)).astype(np.float32)
+    M = bernoulli_mask(Y.shape, missing, seed)
+    return Problem(name, model_str, dict(sizes), 1.0, 0.0, Y, M, init_factors(model_str, sizes, seed),
+                   truth, 1, "negbin", float(phi))
+
+
+def binomial_problem(name, model_str, sizes, n, *, seed, truth_shape, truth_scale=1.0, missing=0.0):
+    """Y ~ Binomial(n, p) with odds p / (1 - p) = einsum(model_str, truth)."""
+    truth = gamma_factors(model_str, sizes, truth_shape, truth_scale, rng(seed, STREAM_TRUTH))
+    odds = mean_tensor(model_str, truth)
+    Y = rng(seed, STREAM_NOISE).binomial(int(n), odds / (1.0 + odds)).astype(np.float32)
+    M = bernoulli_mask(Y.shape, missing, seed)
+    return Problem(name, model_str, dict(sizes), 1.0, 0.0, Y, M, init_factors(model_str, sizes, seed),
+                   truth, 1, "binomial", float(n))
+
+
+def js_problem(name, model_str, sizes, *, seed, truth_shape, missing=0.0):
+    """Poisson counts fitted under the Jensen-Shannon divergence."""
+    p = poisson_problem(name, model_str, sizes, 1.0, 0.0, seed=seed, truth_shape=truth_shape,
+                        missing=missing)
+    p.family = "js"
+    return p
 
 
 # --------------------------------------------------------------------------

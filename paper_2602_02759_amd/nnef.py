@@ -21,6 +21,7 @@ _lib = None
 STATUS = {0: "NNEF_OK", 1: "NNEF_E_PARSE", 2: "NNEF_E_SHAPE", 3: "NNEF_E_LOSS_UNSUPPORTED",
           4: "NNEF_E_ARG", 5: "NNEF_E_DEVICE", 6: "NNEF_E_NOMEM", 7: "NNEF_E_UNSUPPORTED"}
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
+FAMILY = {"ab": 0, "negbin": 1, "binomial": 2, "js": 3}
 
 
 class NnefError(RuntimeError):
@@ -31,7 +32,8 @@ class NnefError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("prec", ctypes.c_int), ("deterministic", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("family", ctypes.c_int), ("reserved", ctypes.c_int * 5),
+                ("family_param", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -153,11 +155,14 @@ def _factor_array(factors, numels=None):
 
 
 # ------------------------------------------------------------------ C-named calls
-def nnef_plan(model_str, mode_sizes, ranks, alpha, beta, eps=1e-10, prec="fp32"):
+def nnef_plan(model_str, mode_sizes, ranks, alpha, beta, eps=1e-10, prec="fp32", family="ab",
+              family_param=0.0):
     opt = Options()
     lib().nnef_default_options(ctypes.byref(opt))
     opt.eps = eps
     opt.prec = PREC[prec]
+    opt.family = FAMILY[family]
+    opt.family_param = float(family_param)
     ms = (ctypes.c_int64 * len(mode_sizes))(*mode_sizes)
     rk = (ctypes.c_int64 * max(1, len(ranks)))(*ranks)
     h = ctypes.c_void_p()
@@ -405,9 +410,11 @@ class Mlp:
 class Plan:
     """Owner of an ``nnef_plan_t``; the methods call the C entry points."""
 
-    def __init__(self, model_str, mode_sizes, ranks, alpha, beta, eps=1e-10, prec="fp32"):
+    def __init__(self, model_str, mode_sizes, ranks, alpha=1.0, beta=0.0, eps=1e-10, prec="fp32",
+                 family="ab", family_param=0.0):
         self.model_str = model_str
-        self.h = nnef_plan(model_str, list(mode_sizes), list(ranks), alpha, beta, eps, prec)
+        self.h = nnef_plan(model_str, list(mode_sizes), list(ranks), alpha, beta, eps, prec, family,
+                           family_param)
         n = lib().nnef_plan_num_factors(self.h)
         self.numels = [lib().nnef_plan_factor_numel(self.h, i) for i in range(n)]
 

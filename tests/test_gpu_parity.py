@@ -35,6 +35,10 @@ def _case(name):
         return datagen.cp3(1.0, 0.0, sizes=dict(i=37, j=29, k=23), R=5, seed=23)
     if name == "cp3_ragged_gen":
         return datagen.cp3(0.7, 0.3, sizes=dict(i=37, j=29, k=23), R=5, seed=24)
+    if name == "cp3_ragged_euc_nomask":  # padded tile entries must count as missing
+        return datagen.cp3(1.0, 1.0, sizes=dict(i=37, j=29, k=23), R=27, seed=27, missing=0.0)
+    if name == "tucker_is_nomask":
+        return datagen.tucker3(I=30, J=26, K=18, Ra=6, Rb=5, Rc=4, seed=33, missing=0.0)
     if name == "cp3_full_euc":
         return datagen.cp3(1.0, 1.0)
     if name == "cp3_full_ab":
@@ -83,7 +87,7 @@ def _case(name):
 
 SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_gen", "tucker_small",
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
-         "hellinger", "is", "shared_letter"]
+         "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask"]
 
 
 @pytest.mark.parametrize("name", SMALL)
