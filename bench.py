@@ -34,9 +34,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--beta", type=float, default=1.0)
-    ap.add_argument("--workload", choices=("cp", "batched", "tucker", "tt"), default="cp",
+    ap.add_argument("--workload", choices=("cp", "batched", "tucker", "tt", "uber", "uber400", "icews"),
+                    default="cp",
                     help="cp: the CP 256^3 headline; batched: 96 CP4 problems x 8 restarts; "
-                         "tucker / tt: the Tucker IS and tensor-train workloads")
+                         "tucker / tt: the Tucker IS and tensor-train workloads; uber / uber400 / icews: "
+                         "the paper's custom strings at its data shapes (synthetic counts)")
     ap.add_argument("--n", type=int, default=256, help="mode size")
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--prec", choices=("fp32", "bf16", "fp16"), default="fp32",
@@ -265,14 +267,17 @@ def bench_batched(args):
 
 
 def bench_single(args):
-    """The Tucker 512x512x128 IS workload or the tensor-train 128x128x96x64 KL
-    workload: plain FP32 and BF16-contraction sweeps/s."""
+    """One of the secondary workloads (Tucker 512x512x128 IS, tensor train
+    128x128x96x64 KL, the Uber and ICEWS strings at the paper's shapes): plain
+    FP32 and BF16-contraction sweeps/s, and time to the plain run's 200-sweep
+    loss."""
     import numpy as np
     import torch
 
     from paper_2602_02759_amd import datagen
     from paper_2602_02759_amd.nnef import Plan
-    p = datagen.tucker3() if args.workload == "tucker" else datagen.tt4()
+    p = {"tucker": datagen.tucker3, "tt": datagen.tt4, "uber": datagen.uber_problem,
+         "uber400": lambda: datagen.uber_problem(mesh=400), "icews": datagen.icews_problem}[args.workload]()
     Y = torch.from_numpy(p.Y).cuda()
     M = torch.from_numpy(p.M).cuda() if p.M is not None else None
     res = {}
@@ -334,7 +339,7 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)
-    if args.workload in ("tucker", "tt"):
+    if args.workload != "cp":
         return bench_single(args)
     import numpy as np
     import torch

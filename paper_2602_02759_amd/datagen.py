@@ -218,3 +218,23 @@ def cp4_problem(dims, R, seed, n_restarts=8):
 
 def random_factors(model_str, sizes, seed, shape=1.0):
     return init_factors(model_str, sizes, seed, shape=shape)
+
+
+# --------------------------------------------------------------------------
+# The paper's custom model strings at its data shapes (Sec. 6: Uber pickups
+# w x d x h x i x j with a spatial mesh, ICEWS country x country x action x
+# time), with synthetic counts standing in for the unavailable datasets.
+# Ranks the paper leaves unstated are this generator's choice.
+# --------------------------------------------------------------------------
+def uber_problem(mesh=100, R=10, K=6, seed=11, missing=0.1):
+    """'wr,dr,hr,irk,jrk->wdhij': 27 weeks x 7 days x 24 hours x mesh x mesh."""
+    sz = {"w": 27, "d": 7, "h": 24, "i": mesh, "j": mesh, "r": R, "k": K}
+    return poisson_problem(f"uber{mesh}", "wr,dr,hr,irk,jrk->wdhij", sz, 1.0, 0.0, seed=seed,
+                           truth_shape=0.3, missing=missing, n_sweeps=100)
+
+
+def icews_problem(R=32, K=8, seed=12, missing=0.1):
+    """'ir,jr,ak,kr,tr->ijat': 249 x 249 countries x 20 action types x 228 months."""
+    sz = {"i": 249, "j": 249, "a": 20, "t": 228, "r": R, "k": K}
+    return poisson_problem("icews", "ir,jr,ak,kr,tr->ijat", sz, 1.0, 0.0, seed=seed,
+                           truth_shape=0.3, missing=missing, n_sweeps=100)

@@ -19,6 +19,7 @@ def _plan(p, prec):
 
 
 CASES = {
+    "tucker_full_is": lambda: datagen.tucker3(),
     "cp3_full_euc": lambda: datagen.cp3(1.0, 1.0),
     "cp3_full_ab": lambda: datagen.cp3(0.5, 1.0),
     "cp3_small_kl": lambda: datagen.cp3(1.0, 0.0, sizes=dict(i=48, j=40, k=36), R=32, seed=25),

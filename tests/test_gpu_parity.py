@@ -130,6 +130,31 @@ def test_full_size_cp3_step(name):
     assert_step_parity(g1, oracle_sweep(p, s0), TOL, name)
 
 
+@pytest.mark.parametrize("name", ["tucker_full", "tt_full", "uber_paper_shape"])
+def test_full_size_step(name):
+    """The Tucker 512x512x128 IS and tensor-train 128x128x96x64 workloads and
+    the Uber string at the paper's data shape: one sweep vs the oracle."""
+    p = {"tucker_full": datagen.tucker3, "tt_full": datagen.tt4,
+         "uber_paper_shape": datagen.uber_problem}[name]()
+    print(f"[parity] {name} {p.model_str} {p.sizes}", flush=True)
+    plan = _plan(p)
+    print(plan.describe(), flush=True)
+    s0 = clamp_init(p)
+    g1 = gpu_sweeps(plan, p, s0, 1)
+    assert_step_parity(g1, oracle_sweep(p, s0), TOL, name)
+
+
+def test_icews_paper_shape_loss():
+    """ICEWS string at the paper's shape (283 M entries): the loss of the
+    initial factors vs the oracle."""
+    p = datagen.icews_problem()
+    plan = _plan(p)
+    s0 = clamp_init(p)
+    got = plan.loss(to_dev(p.Y), to_dev(p.M), [to_dev(s) for s in s0])
+    ref = O.loss(p.model_str, [s.astype(np.float64) for s in s0], p.Y, p.M, p.alpha, p.beta)
+    assert abs(got - ref) <= 1e-5 * abs(ref), (got, ref)
+
+
 def test_nmf_trajectory_final_loss():
     """Config 1 (NMF KL 200x150 R=8): 100 sweeps; per-step parity at t in
     {0, 1, 10, 99} and final loss within 1e-4 of the oracle's own run."""
