@@ -382,6 +382,7 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.n_chunks = bp.n_chunks;
   a.n_wg = bp.n_wg;
   a.xcd_remap = bp.xcd_remap;
+  a.wave_rows = bp.wave_rows;
   a.partN = p->partN;
   a.partD = p->partD;
   a.no_d = (p->ls.b_is_one() && !masked && bp.pieces_disjoint) ? 1 : 0;

@@ -72,8 +72,13 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   int b = braw;
   if (a.xcd_remap) b = (b & 7) * (a.n_wg >> 3) + (b >> 3);
   const int panel = b % a.n_panels, chunk = b / a.n_panels;
-  const int p0 = panel * ROWS;
-  const int64_t s_beg = ((int64_t)chunk * 4 + wave) * a.steps_per_wave;
+  // wave_rows: the four waves take four consecutive 32-row panels over the same
+  // steps (for blocks with many rows and few column steps); otherwise they
+  // share one panel and split the steps
+  const bool wrows = a.wave_rows != 0;
+  const int p0 = wrows ? (panel * 4 + wave) * ROWS : panel * ROWS;
+  const int64_t s_beg = wrows ? (int64_t)chunk * a.steps_per_wave
+                              : ((int64_t)chunk * 4 + wave) * a.steps_per_wave;
   const int64_t s_end = s_beg + a.steps_per_wave < a.n_steps ? s_beg + a.steps_per_wave : a.n_steps;
 
   const int p = p0 + c;
@@ -418,6 +423,15 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
     // accumulator register v holds X^T[k = 8(v/4) + 4g + v%4][p = p0 + c]; waves
     // 1..3 stash theirs, wave 0 adds them in a fixed order and stores the partial
     auto store = [&](const f16v& acc, float* dst) {
+      if (wrows) {  // each wave owns its rows
+        if (p < a.nP) {
+#pragma unroll
+          for (int bq = 0; bq < 4; ++bq)
+            *reinterpret_cast<f4*>(&dst[((size_t)chunk * a.nP + p) * KP + 8 * bq + 4 * g]) =
+                f4{acc[4 * bq], acc[4 * bq + 1], acc[4 * bq + 2], acc[4 * bq + 3]};
+        }
+        return;
+      }
       if (wave > 0) {
 #pragma unroll
         for (int bq = 0; bq < 4; ++bq)

@@ -79,6 +79,7 @@ struct FusedArgs {
   int n_chunks;                // partial slots
   int n_wg;                    // grid size
   int xcd_remap;               // 1: consecutive work items share an XCD
+  int wave_rows;               // width 32: each wave its own 32 rows, all waves the same steps
   float* partN;                // [n_chunks][nP][KP]
   float* partD;                // [n_chunks][nP][KP] (unused when no_d)
   double* loss_part;           // [n_wg] (loss passes)

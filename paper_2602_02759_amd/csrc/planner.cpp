@@ -564,17 +564,21 @@ std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, con
 bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg) {
   (void)m;
   bp.qstep = (bp.KP == 32 && kX32) ? 32 : 16;
-  bp.rows = bp.KP == 16 ? 64 : bp.KP == 32 ? (kX32 ? 32 : 16 * kPT32) : 16;
-  const int rows = bp.rows;
-  bp.n_panels = (int)((bp.nP + rows - 1) / rows);
   const int64_t nqis = (bp.nqi + bp.qstep - 1) / bp.qstep;
   bp.n_steps = bp.nqo * nqis;
+  // many rows and few column steps: give each wave its own rows, so that a
+  // wave runs all steps of its chunk instead of a quarter of them
+  bp.wave_rows = (bp.KP == 32 && kX32 && bp.n_steps <= 64 && bp.nP >= 4096) ? 1 : 0;
+  bp.rows = bp.KP == 16 ? 64 : bp.KP == 32 ? (kX32 ? (bp.wave_rows ? 128 : 32) : 16 * kPT32) : 16;
+  const int rows = bp.rows;
+  bp.n_panels = (int)((bp.nP + rows - 1) / rows);
+  const int split = bp.wave_rows ? 1 : 4;  // waves sharing a chunk's steps
   int64_t chunks = std::max<int64_t>(1, (target_wg + bp.n_panels - 1) / bp.n_panels);
-  chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (bp.n_steps + 3) / 4));
-  const int64_t spw = (bp.n_steps + 4 * chunks - 1) / (4 * chunks);
+  chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (bp.n_steps + split - 1) / split));
+  const int64_t spw = (bp.n_steps + split * chunks - 1) / (split * chunks);
   if (spw >= (int64_t(1) << 31)) return false;
   bp.steps_per_wave = (int)spw;
-  bp.n_chunks = (int)((bp.n_steps + 4 * spw - 1) / (4 * spw));
+  bp.n_chunks = (int)((bp.n_steps + split * spw - 1) / (split * spw));
   const int64_t nwg = (int64_t)bp.n_panels * bp.n_chunks;
   if (nwg >= (int64_t(1) << 31)) return false;
   bp.n_wg = (int)nwg;
@@ -617,7 +621,7 @@ std::string describe_block(const Model& m, const BlockPlan& bp) {
   }
   o << (bp.L_direct ? "" : " chain-back") << " qo={" << bp.qo << "} qi=" << (bp.qi ? bp.qi : '-')
     << (bp.vecq ? " vecq" : "") << " grid=" << bp.n_wg << " chunks=" << bp.n_chunks
-    << " steps/wave=" << bp.steps_per_wave;
+    << " steps/wave=" << bp.steps_per_wave << (bp.wave_rows ? " wave-rows" : "");
   return o.str();
 }
 

@@ -84,6 +84,7 @@ struct BlockPlan {
   int n_panels = 0, steps_per_wave = 0, n_chunks = 0, n_wg = 0;
   int64_t n_steps = 0;
   int xcd_remap = 0;
+  int wave_rows = 0;  // width 32: waves take separate row panels over the same steps
   uint32_t* d_poff = nullptr;
   uint32_t* d_qoyoff = nullptr;
   uint32_t* d_inbase = nullptr;    // nullptr: all zero

@@ -70,6 +70,14 @@ def _case(name):
         return datagen.poisson_problem("icews", "ir,jr,ak,kr,tr->ijat",
                                        dict(i=12, j=12, a=5, t=9, r=6, k=2), 1.3, 1.0, seed=63,
                                        truth_shape=0.5, missing=0.1)
+    if name == "icews_tall":  # many rows, few column steps: one row panel per wave (ragged)
+        return datagen.poisson_problem("icews_tall", "ir,jr,ak,kr,tr->ijat",
+                                       dict(i=40, j=40, a=10, t=12, r=32, k=4), 1.0, 1.0, seed=68,
+                                       truth_shape=0.5, missing=0.1)
+    if name == "icews_tall_full":  # the same on full tiles
+        return datagen.poisson_problem("icews_tall_full", "ir,jr,ak,kr,tr->ijat",
+                                       dict(i=64, j=64, a=8, t=16, r=32, k=4), 1.0, 0.0, seed=69,
+                                       truth_shape=0.5, missing=0.1)
     if name == "shared_letter":  # column-side pieces 'jr' and 'jkr' share j
         return datagen.poisson_problem("shl", "ir,jr,jkr->ijk", dict(i=21, j=18, k=20, r=5),
                                        1.0, 0.0, seed=67, truth_shape=0.5)
@@ -87,7 +95,7 @@ def _case(name):
 
 SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_gen", "tucker_small",
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
-         "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask"]
+         "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full"]
 
 
 @pytest.mark.parametrize("name", SMALL)
