@@ -402,3 +402,46 @@ def kkt_residual(model_str, factors, Y, M, alpha, beta, eps):
         v_floor = float(np.max(np.maximum(0.0, sgn * (r[at_floor] - 1.0)), initial=0.0))
         worst = max(worst, v_int + v_floor)
     return worst
+
+
+# --------------------------------------------------------------------------
+# Train / validation splits and the stopping rule (Sec. 6, "Experimental
+# design"; App. A, "Stopping criterion")
+# --------------------------------------------------------------------------
+STOP_MAX, STOP_TRAIN_TOL, STOP_VALIDATION = 0, 1, 2
+
+
+def stop_reason(t, L, V, patience, rel_tol, max_sweeps):
+    """The rule for state t given the losses L[0..t], V[0..t] (V None: no
+    validation set): the validation loss rose `patience` times in a row, the
+    training loss fell by less than rel_tol relative, or t reached the cap.
+    Checked in that order; None if no rule applies."""
+    if V is not None and patience > 0 and t >= patience and \
+            all(V[t - q] > V[t - q - 1] for q in range(patience)):
+        return STOP_VALIDATION
+    if t >= 1 and (L[t - 1] - L[t]) < rel_tol * abs(L[t - 1]):
+        return STOP_TRAIN_TOL
+    if t >= max_sweeps:
+        return STOP_MAX
+    return None
+
+
+def fit_early_stopping(model_str, factors, Y, M, alpha, beta, eps=1e-10, max_sweeps=5000,
+                       patience=5, rel_tol=1e-6, train_value=1, val_value=2):
+    """Algorithm 1 on the entries with mask byte train_value, stopped by the
+    rules above.  Returns (factors of the stopping state, t, reason, L, V)."""
+    M = np.asarray(M)
+    Mt = (M == train_value).astype(np.uint8)
+    Mv = (M == val_value).astype(np.uint8) if val_value else None
+    f = [np.maximum(np.asarray(t, dtype=np.float64), eps) for t in factors]
+    L, V = [], ([] if Mv is not None else None)
+    t = 0
+    while True:
+        L.append(loss(model_str, f, Y, Mt, alpha, beta))
+        if V is not None:
+            V.append(loss(model_str, f, Y, Mv, alpha, beta))
+        r = stop_reason(t, L, V, patience, rel_tol, max_sweeps)
+        if r is not None:
+            return f, t, r, L, V
+        f = sweep(model_str, f, Y, Mt, alpha, beta, eps)
+        t += 1

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-STREAM_TRUTH, STREAM_NOISE, STREAM_MASK, STREAM_INIT = 0, 1, 2, 3
+STREAM_TRUTH, STREAM_NOISE, STREAM_MASK, STREAM_INIT, STREAM_SPLIT = 0, 1, 2, 3, 4
 
 
 def rng(seed: int, stream: int) -> np.random.Generator:
@@ -89,6 +89,17 @@ def bernoulli_mask(shape, missing, seed):
         return None
     g = rng(seed, STREAM_MASK)
     return (g.random(size=shape) >= missing).astype(np.uint8)
+
+
+def split_mask(shape, seed, heldout=0.10, validation=0.05):
+    """Split of Sec. 6: each entry is heldout (3) with probability `heldout`,
+    else in training; a `validation` fraction of the training entries is
+    validation (2); the rest are fitted (1)."""
+    u = rng(seed, STREAM_SPLIT).random(size=(2,) + tuple(shape))
+    m = np.ones(shape, dtype=np.uint8)
+    m[u[1] < validation] = 2
+    m[u[0] < heldout] = 3
+    return m
 
 
 def mean_tensor(model_str, factors):
