@@ -23,7 +23,7 @@
  *   never frees or reallocates them.  Layouts are dense row-major:
  *     Y, mask : axes in the order of the output letters of the model string;
  *     factor l: axes in the order of operand l's subscripts.
- *   Y is float32; mask is uint8 with 1 = observed, 0 = missing (NULL = fully
+ *   Y is float32; mask is uint8 with 1 = observed, any other value = not used (NULL = fully
  *   observed).  Factors are float32 and are updated in place.
  *   `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Entry points only enqueue work on that stream, except where a comment
@@ -308,6 +308,58 @@ nnef_status nnef_batch_autotune(nnef_batch_t batch, const float* const* Y, const
 
 /* Lowering of every problem and the tiling chosen (as nnef_plan_describe). */
 size_t nnef_batch_describe(nnef_batch_t batch, char* buf, size_t buf_len);
+
+/* ------------------------------------------------------------------------
+ * Splits and early stopping (Sec. 6, "Experimental design"; App. A,
+ * "Stopping criterion").  A split mask holds one byte per entry: entries
+ * equal to train_value (default 1) are fitted, val_value (default 2) marks
+ * the validation set, any other value (0 missing, 3 heldout, ...) is unused.
+ * The mask passed to nnef_step and nnef_loss follows the same rule: only
+ * entries equal to 1 are observed.
+ * ------------------------------------------------------------------------ */
+
+/* Loss over the entries whose mask byte equals `value` (e.g. 2 validation,
+ * 3 heldout), written to *d_loss (device); uses the plan's packing buffer. */
+nnef_status nnef_loss_split(nnef_plan_t plan, const float* Y, const uint8_t* mask, int value,
+                            const float* const* factors, double* d_loss, void* stream);
+
+typedef enum { NNEF_STOP_MAX = 0, NNEF_STOP_TRAIN_TOL = 1, NNEF_STOP_VALIDATION = 2 } nnef_stop_reason;
+
+typedef struct {
+  int    max_sweeps;   /* sweep cap; default 5000                                        */
+  int    patience;     /* stop when the validation loss rose this many sweeps in a row;
+                          default 5, 0 disables                                          */
+  double rel_tol;      /* stop when (L_{t-1} - L_t) / L_{t-1} < rel_tol for the training
+                          loss; default 1e-6                                             */
+  int    check_every;  /* losses are read back every check_every sweeps; 1 (default)
+                          stops exactly at the first state that meets a rule, larger
+                          values run up to check_every - 1 sweeps past it             */
+  int    train_value;  /* mask byte of training entries; default 1                       */
+  int    val_value;    /* mask byte of validation entries; default 2, 0 = none           */
+} nnef_fit_options;
+
+typedef struct {
+  int    stop_sweep;   /* t of the state theta_t that met a rule (0 = the input state)  */
+  int    sweeps_run;   /* sweeps applied to the factors (>= stop_sweep)                  */
+  int    reason;       /* nnef_stop_reason; checked in the order validation, training, cap */
+  double train_loss;   /* losses of theta_{stop_sweep}                                   */
+  double val_loss;
+} nnef_fit_result;
+
+void nnef_default_fit_options(nnef_fit_options* opt);
+
+/*
+ * Fit with the paper's stopping rules: for t = 0, 1, ... the training and
+ * validation losses of theta_t are taken (float32 terms, float64 sums), the
+ * rules are checked, and otherwise one sweep is run on the training entries.
+ * train_trace / val_trace (device, may be NULL) receive the losses of
+ * theta_0 .. theta_{stop_sweep}; they need room for max_sweeps + 1 doubles.
+ * Allocates a packed copy of the validation data for the call and
+ * synchronises the stream.
+ */
+nnef_status nnef_fit(nnef_plan_t plan, const float* Y, const uint8_t* mask, float* const* factors,
+                     const nnef_fit_options* opt, nnef_fit_result* res, double* train_trace,
+                     double* val_trace, void* stream);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* nnef_last_error(void);

@@ -571,6 +571,130 @@ nnef_status nnef_loss(nnef_plan_t p, const float* Y, const uint8_t* M, const flo
 }
 
 // ---------------------------------------------------------------------------
+// Train / validation / heldout splits and the stopping rule
+nnef_status nnef_loss_split(nnef_plan_t p, const float* Y, const uint8_t* M, int value,
+                            const float* const* factors, double* d_loss, void* stream) {
+  if (!p || !Y || !M || !factors || !d_loss) return fail(NNEF_E_ARG, "NULL argument");
+  if (value < 0 || value > 255) return fail(NNEF_E_ARG, "value must be a mask byte");
+  for (int l = 0; l < (int)p->m.ops.size(); ++l)
+    if (!factors[l]) return fail(NNEF_E_ARG, "factor pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int e = launch_pack(Y, M, p->ypack, p->n_data, s, value);
+  if (e) return hip_fail(e, "data packing launch");
+  return run_loss(p, p->ypack, true, factors, d_loss, s);
+}
+
+void nnef_default_fit_options(nnef_fit_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_sweeps = 5000;
+  o->patience = 5;
+  o->rel_tol = 1e-6;
+  o->check_every = 1;
+  o->train_value = 1;
+  o->val_value = 2;
+}
+
+nnef_status nnef_fit(nnef_plan_t p, const float* Y, const uint8_t* M, float* const* factors,
+                     const nnef_fit_options* opt_in, nnef_fit_result* res, double* train_trace,
+                     double* val_trace, void* stream) {
+  nnef_status st = check_step_args(p, Y, factors, 0);
+  if (st != NNEF_OK) return st;
+  if (!M || !res) return fail(NNEF_E_ARG, "mask and res must not be NULL");
+  nnef_fit_options o;
+  nnef_default_fit_options(&o);
+  if (opt_in) o = *opt_in;
+  if (o.max_sweeps < 0 || o.patience < 0 || o.check_every < 1 || !(o.rel_tol >= 0) ||
+      o.train_value < 0 || o.train_value > 255 || o.val_value < 0 || o.val_value > 255 ||
+      (o.val_value != 0 && o.val_value == o.train_value))
+    return fail(NNEF_E_ARG, "invalid fit options");
+  hipStream_t s = (hipStream_t)stream;
+  const bool use_val = o.val_value != 0;
+  // per state: training and validation losses (device), read back in chunks
+  const int k = o.check_every;
+  float* yval = nullptr;
+  double* dl = nullptr;
+  if ((use_val && hipMalloc((void**)&yval, (size_t)p->n_data * sizeof(float)) != hipSuccess) ||
+      hipMalloc((void**)&dl, 2 * (size_t)k * sizeof(double)) != hipSuccess) {
+    if (yval) (void)hipFree(yval);
+    return fail(NNEF_E_NOMEM, "fit buffers");
+  }
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    if (yval) (void)hipFree(yval);
+    (void)hipFree(dl);
+  };
+  int e = launch_pack(Y, M, p->ypack, p->n_data, s, o.train_value);
+  if (!e && use_val) e = launch_pack(Y, M, yval, p->n_data, s, o.val_value);
+  if (e) {
+    cleanup();
+    return hip_fail(e, "data packing launch");
+  }
+  std::vector<double> L, V, hl(2 * (size_t)k);
+  int run = 0, stop = -1, reason = NNEF_STOP_MAX;
+  for (int s0 = 0; stop < 0; s0 += k) {
+    const int cnt = std::min(k, o.max_sweeps - s0 + 1);
+    // states s0 .. s0 + cnt - 1: losses of each, a sweep between consecutive ones
+    for (int j = 0; j < cnt; ++j) {
+      if (j > 0) {
+        st = run_sweep(p, p->ypack, true, factors, nullptr, s);
+        if (st == NNEF_OK) ++run;
+      }
+      if (st == NNEF_OK) st = run_loss(p, p->ypack, true, factors, dl + j, s);
+      if (st == NNEF_OK && use_val) st = run_loss(p, yval, true, factors, dl + k + j, s);
+      if (st != NNEF_OK) {
+        cleanup();
+        return st;
+      }
+    }
+    if (hipMemcpyAsync(hl.data(), dl, hl.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      cleanup();
+      return fail(NNEF_E_DEVICE, "loss read-back failed");
+    }
+    for (int j = 0; j < cnt && stop < 0; ++j) {
+      const int t = s0 + j;
+      L.push_back(hl[j]);
+      V.push_back(use_val ? hl[k + j] : 0.0);
+      // the paper's rules: validation loss rising `patience` times in a row,
+      // relative decrease of the training loss below rel_tol, or the sweep cap
+      bool rising = use_val && o.patience > 0 && t >= o.patience;
+      for (int q = 0; rising && q < o.patience; ++q) rising = V[t - q] > V[t - q - 1];
+      if (rising) {
+        stop = t;
+        reason = NNEF_STOP_VALIDATION;
+      } else if (t >= 1 && (L[t - 1] - L[t]) < o.rel_tol * std::fabs(L[t - 1])) {
+        stop = t;
+        reason = NNEF_STOP_TRAIN_TOL;
+      } else if (t >= o.max_sweeps) {
+        stop = t;
+        reason = NNEF_STOP_MAX;
+      }
+    }
+    if (stop < 0) {  // advance to the first state of the next chunk
+      st = run_sweep(p, p->ypack, true, factors, nullptr, s);
+      if (st != NNEF_OK) {
+        cleanup();
+        return st;
+      }
+      ++run;
+    }
+  }
+  if (train_trace && hipMemcpyAsync(train_trace, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+    st = fail(NNEF_E_DEVICE, "trace copy failed");
+  if (val_trace && use_val &&
+      hipMemcpyAsync(val_trace, V.data(), V.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+    st = fail(NNEF_E_DEVICE, "trace copy failed");
+  cleanup();
+  res->stop_sweep = stop;
+  res->sweeps_run = run;
+  res->reason = reason;
+  res->train_loss = L[stop];
+  res->val_loss = use_val ? V[stop] : 0.0;
+  return st;
+}
+
+// ---------------------------------------------------------------------------
 // Learned extrapolation
 struct nnef_mlp_s {
   float* params = nullptr;   // FP32 master parameters

@@ -244,20 +244,18 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
 // at a missing entry is never read into arithmetic, only replaced.
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Y,
                                                    const uint8_t* __restrict__ M,
-                                                   float* __restrict__ Yp, int64_t n) {
+                                                   float* __restrict__ Yp, int64_t n, uint32_t value) {
   typedef float v4 __attribute__((ext_vector_type(4)));
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i + 3 < n) {
     const v4 y = *reinterpret_cast<const v4*>(Y + i);
     const uint32_t m = *reinterpret_cast<const uint32_t*>(M + i);
     v4 o;
-    o[0] = (m & 0xffu) ? y[0] : -1.f;
-    o[1] = (m & 0xff00u) ? y[1] : -1.f;
-    o[2] = (m & 0xff0000u) ? y[2] : -1.f;
-    o[3] = (m & 0xff000000u) ? y[3] : -1.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = ((m >> (8 * j)) & 0xffu) == value ? y[j] : -1.f;
     *reinterpret_cast<v4*>(Yp + i) = o;
   } else {
-    for (int64_t j = i; j < n; ++j) Yp[j] = M[j] ? Y[j] : -1.f;
+    for (int64_t j = i; j < n; ++j) Yp[j] = M[j] == value ? Y[j] : -1.f;
   }
 }
 
@@ -353,11 +351,11 @@ int launch_loss_final(const double* part, int n, double* out, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream) {
+int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream, int value) {
   if (n <= 0) return 0;
   const int64_t threads = (n + 3) / 4;
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, Y, M, Yp, n);
+                     (hipStream_t)stream, Y, M, Yp, n, (uint32_t)value);
   return (int)hipGetLastError();
 }
 

@@ -159,8 +159,8 @@ int launch_apply(const ApplyArgs& a, void* stream);
 int launch_loss_final(const double* part, int n, double* out, void* stream);
 int launch_zero(float* p, int64_t n, void* stream);
 int launch_copy_f64(double* dst, const double* src, int n, void* stream);
-// Yp[i] = mask[i] ? Y[i] : -1 (observed data are nonnegative).
-int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream);
+// Yp[i] = mask[i] == value ? Y[i] : -1 (observed data are nonnegative).
+int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream, int value = 1);
 
 // ---- learned extrapolation (a small MLP over per-element trajectory features)
 constexpr int kMlpIn = 8, kMlpWidth = 128;

@@ -43,6 +43,16 @@ class Problem(ctypes.Structure):
                 ("n_restarts", ctypes.c_int), ("masked", ctypes.c_int)]
 
 
+class FitOptions(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int), ("patience", ctypes.c_int), ("rel_tol", ctypes.c_double),
+                ("check_every", ctypes.c_int), ("train_value", ctypes.c_int), ("val_value", ctypes.c_int)]
+
+
+class FitResult(ctypes.Structure):
+    _fields_ = [("stop_sweep", ctypes.c_int), ("sweeps_run", ctypes.c_int), ("reason", ctypes.c_int),
+                ("train_loss", ctypes.c_double), ("val_loss", ctypes.c_double)]
+
+
 EXPORTS = {
     "nnef_default_options": (None, [ctypes.POINTER(Options)]),
     "nnef_plan": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
@@ -77,6 +87,13 @@ EXPORTS = {
                                            ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "nnef_batch_describe": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
+    "nnef_loss_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_default_fit_options": (None, [ctypes.POINTER(FitOptions)]),
+    "nnef_fit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(FitOptions),
+                                ctypes.POINTER(FitResult), ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p]),
     "nnef_mlp_num_params": (ctypes.c_int, []),
     "nnef_mlp_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "nnef_mlp_destroy": (None, [ctypes.c_void_p]),
@@ -365,6 +382,32 @@ class Batch:
             pass
 
 
+def nnef_loss_split(h, Y, M, value, factors, d_out, stream=None):
+    import torch
+    _check(lib().nnef_loss_split(h, _ptr(Y, torch.float32, "Y"), _ptr(M, torch.uint8, "mask"), int(value),
+                                 _factor_array(factors), _ptr(d_out, torch.float64, "d_out"),
+                                 _stream(stream)))
+
+
+def nnef_fit(h, Y, M, factors, train_trace=None, val_trace=None, stream=None, **options):
+    """Options: max_sweeps, patience, rel_tol, check_every, train_value, val_value."""
+    import torch
+    opt = FitOptions()
+    lib().nnef_default_fit_options(ctypes.byref(opt))
+    for k, v in options.items():
+        if not hasattr(opt, k):
+            raise TypeError(f"unknown fit option {k}")
+        setattr(opt, k, v)
+    res = FitResult()
+    _check(lib().nnef_fit(h, _ptr(Y, torch.float32, "Y"), _ptr(M, torch.uint8, "mask"),
+                          _factor_array(factors), ctypes.byref(opt), ctypes.byref(res),
+                          _ptr(train_trace, torch.float64, "train_trace"),
+                          _ptr(val_trace, torch.float64, "val_trace"), _stream(stream)))
+    return {"stop_sweep": res.stop_sweep, "sweeps_run": res.sweeps_run,
+            "reason": {0: "max_sweeps", 1: "train_tol", 2: "validation"}[res.reason],
+            "train_loss": res.train_loss, "val_loss": res.val_loss}
+
+
 class Mlp:
     """Owner of an ``nnef_mlp_t`` (the extrapolation network)."""
 
@@ -448,6 +491,18 @@ class Plan:
         self._check_factors(factors)
         nnef_step_learned(self.h, mlp.h, Y, M, factors, n_sweeps, propose_every, loss_trace,
                           n_accepted, stream)
+
+    def loss_split(self, Y, M, value, factors):
+        """Loss over the entries whose mask byte equals ``value`` (syncs)."""
+        import torch
+        self._check_factors(factors)
+        out = torch.empty(1, dtype=torch.float64, device=Y.device)
+        nnef_loss_split(self.h, Y, M, value, factors, out)
+        return out.item()
+
+    def fit(self, Y, M, factors, train_trace=None, val_trace=None, **options):
+        self._check_factors(factors)
+        return nnef_fit(self.h, Y, M, factors, train_trace, val_trace, **options)
 
     def set_timing(self, enable=True):
         nnef_plan_set_timing(self.h, enable)
