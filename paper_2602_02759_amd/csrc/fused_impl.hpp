@@ -381,10 +381,19 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
       const int qac = qa < a.nqi ? qa : a.nqi - 1;
       const uint32_t ra = (ibase + (uint32_t)qac * in_stride) * ld_in;
       const bool va = qa < a.nqi;
+      if (vec_in) {  // full-width rows: float4 loads, only the row is clamped
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const float v = ldf(a.inner, ra + kA[s]);
-        d.Ra[s] = (va && g * KS + s < a.K) ? v : 0.f;
+        for (int s = 0; s < KS; s += 4) {
+          const f4 v = ldf4(a.inner, ra + g * KS + s);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) d.Ra[s + j] = va ? v[j] : 0.f;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const float v = ldf(a.inner, ra + kA[s]);
+          d.Ra[s] = (va && g * KS + s < a.K) ? v : 0.f;
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {

@@ -142,11 +142,20 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
       const int qa = qi0 + c;
       const bool va = qa < a.nqi;
       const uint32_t ra = (ibase + (uint32_t)(va ? qa : a.nqi - 1) * in_stride) * ld_in;
+      if (a.K == KP && (ld_in & 3u) == 0) {  // full-width rows: float4 loads
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int k = 16 * g + s;
-        const float v = ldf(a.inner, ra + (uint32_t)min(k, a.K - 1));
-        d.Ra[s] = (va && k < a.K) ? v : 0.f;
+        for (int s = 0; s < 16; s += 4) {
+          const f4 v = ldf4(a.inner, ra + 16u * g + s);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) d.Ra[s + j] = va ? v[j] : 0.f;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int k = 16 * g + s;
+          const float v = ldf(a.inner, ra + (uint32_t)min(k, a.K - 1));
+          d.Ra[s] = (va && k < a.K) ? v : 0.f;
+        }
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
