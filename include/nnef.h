@@ -120,6 +120,17 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
 
 void nnef_plan_destroy(nnef_plan_t plan);
 
+/*
+ * nnef_plan_dry - the planning of nnef_plan without any device work: parses,
+ * validates and lowers the model and chooses the tiling, then writes the text
+ * nnef_plan_describe would give (at most buf_len - 1 characters) and returns
+ * its full length.  *status receives what nnef_plan would return (0 length
+ * on error).  Needs no GPU.
+ */
+size_t nnef_plan_dry(const char* model_str, const int64_t* mode_sizes, int n_modes,
+                     const int64_t* ranks, int n_ranks, double alpha, double beta,
+                     const nnef_options* opt, nnef_status* status, char* buf, size_t buf_len);
+
 /* Number of factors L, and the number of elements of factor l (0-based). */
 int     nnef_plan_num_factors(nnef_plan_t plan);
 int64_t nnef_plan_factor_numel(nnef_plan_t plan, int l);

@@ -129,7 +129,7 @@ static nnef_status upload_table(nnef_plan_s* p, const std::vector<uint32_t>& t, 
 static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes, int n_modes,
                                const int64_t* ranks, int n_ranks, double alpha, double beta,
                                const nnef_options* opt, bool with_pack, int target_wg,
-                               nnef_plan_t* out, bool direct_only = false) {
+                               nnef_plan_t* out, bool direct_only = false, bool dry_run = false) {
   if (!model_str || !out) return fail(NNEF_E_ARG, "model_str and out must not be NULL");
   *out = nullptr;
   auto* p = new nnef_plan_s();
@@ -225,6 +225,16 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
     free_plan(p);
     return fail(NNEF_E_SHAPE, "partial sums need 2^30 or more elements");
   }
+  if (dry_run) {  // lowering and geometry only: no device memory
+    for (const auto& bp : p->blocks) {
+      const bool lp = bp.KP == 32 && bp.qstep == 32 && p->opt.prec != NNEF_FP32;
+      p->description += describe_block(m, bp) +
+                        (lp ? (p->opt.prec == NNEF_BF16 ? " contract=bf16" : " contract=fp16") : " contract=fp32") +
+                        "\n";
+    }
+    *out = p;
+    return NNEF_OK;
+  }
   // ---- device memory
   size_t ws_total = 0;
   for (auto s : p->ws_sizes) ws_total += (size_t)((s + 63) / 64 * 64);
@@ -295,6 +305,19 @@ nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_mo
                       const nnef_options* opt, nnef_plan_t* out) {
   return plan_create(model_str, mode_sizes, n_modes, ranks, n_ranks, alpha, beta, opt, true,
                      env_int("NNEF_TARGET_WG", 512), out);
+}
+
+size_t nnef_plan_dry(const char* model_str, const int64_t* mode_sizes, int n_modes, const int64_t* ranks,
+                     int n_ranks, double alpha, double beta, const nnef_options* opt, nnef_status* status,
+                     char* buf, size_t buf_len) {
+  nnef_plan_t p = nullptr;
+  const nnef_status st = plan_create(model_str, mode_sizes, n_modes, ranks, n_ranks, alpha, beta, opt,
+                                     false, env_int("NNEF_TARGET_WG", 512), &p, false, true);
+  if (status) *status = st;
+  if (st != NNEF_OK) return 0;
+  const size_t n = nnef_plan_describe(p, buf, buf_len);
+  free_plan(p);
+  return n;
 }
 
 // ---------------------------------------------------------------------------

@@ -60,6 +60,10 @@ EXPORTS = {
                                  ctypes.c_double, ctypes.POINTER(Options),
                                  ctypes.POINTER(ctypes.c_void_p)]),
     "nnef_plan_destroy": (None, [ctypes.c_void_p]),
+    "nnef_plan_dry": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.c_char_p, ctypes.c_size_t]),
     "nnef_plan_num_factors": (ctypes.c_int, [ctypes.c_void_p]),
     "nnef_plan_factor_numel": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int]),
     "nnef_plan_describe": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
@@ -186,6 +190,27 @@ def nnef_plan(model_str, mode_sizes, ranks, alpha, beta, eps=1e-10, prec="fp32",
     _check(lib().nnef_plan(model_str.encode(), ms, len(mode_sizes), rk, len(ranks),
                            float(alpha), float(beta), ctypes.byref(opt), ctypes.byref(h)))
     return h
+
+
+def nnef_plan_dry(model_str, mode_sizes, ranks, alpha=1.0, beta=0.0, eps=1e-10, prec="fp32", family="ab",
+                  family_param=0.0):
+    """Lowering description of a plan, computed without a GPU."""
+    opt = Options()
+    lib().nnef_default_options(ctypes.byref(opt))
+    opt.eps = eps
+    opt.prec = PREC[prec]
+    opt.family = FAMILY[family]
+    opt.family_param = float(family_param)
+    ms = (ctypes.c_int64 * max(1, len(mode_sizes)))(*mode_sizes)
+    rk = (ctypes.c_int64 * max(1, len(ranks)))(*ranks)
+    st = ctypes.c_int()
+    args = (model_str.encode(), ms, len(mode_sizes), rk, len(ranks), float(alpha), float(beta),
+            ctypes.byref(opt), ctypes.byref(st))
+    n = lib().nnef_plan_dry(*args, None, 0)
+    _check(st.value)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().nnef_plan_dry(*args, buf, n + 1)
+    return buf.value.decode()
 
 
 def nnef_plan_destroy(h):

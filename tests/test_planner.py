@@ -1,0 +1,109 @@
+"""The planner (host code of libnnef) without a GPU, through nnef_plan_dry:
+which lowering each block gets, the tile geometry, and its invariants."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.skipif(
+    not os.path.exists(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                    "paper_2602_02759_amd", "libnnef.so")),
+    reason="libnnef.so is not built")
+
+
+def dry(*args, **kw):
+    from paper_2602_02759_amd.nnef import nnef_plan_dry
+    return [parse(line) for line in nnef_plan_dry(*args, **kw).strip().splitlines()]
+
+
+def parse(line):
+    d = {"op": re.search(r"'([a-zA-Z]+)'", line).group(1)}
+    for key in ("P", "Q", "kappa", "qo"):
+        d[key] = re.search(rf"\b{key}={{([a-zA-Z]*)}}", line).group(1)
+    for key in ("K", "KP", "nP", "nQ", "grid", "chunks", "steps/wave"):
+        d[key] = int(re.search(rf"\b{re.escape(key)}=(\d+)", line).group(1))
+    d["L"] = re.search(r"\bL=(\w+)", line).group(1)
+    d["R"] = re.search(r"\bR=(materialised|product\([a-zA-Z,]+\))", line).group(1)
+    d["qi"] = re.search(r"\bqi=([a-zA-Z-])", line).group(1)
+    d["contract"] = re.search(r"contract=(\w+)", line).group(1)
+    d["vecq"] = " vecq" in line
+    d["chain"] = "chain-back" in line
+    d["wave_rows"] = "wave-rows" in line
+    return d
+
+
+def test_cp3_headline_lowering():
+    b = dry("ir,jr,kr->ijk", [256, 256, 256], [32], 1.0, 1.0)
+    assert [x["op"] for x in b] == ["ir", "jr", "kr"]
+    for x, (p, rest) in zip(b, [("i", "jr,kr"), ("j", "ir,kr"), ("k", "ir,jr")]):
+        assert x["P"] == p and x["L"] == "direct" and x["R"] == f"product({rest})" and not x["chain"]
+        assert (x["K"], x["KP"], x["nP"], x["nQ"]) == (32, 32, 256, 65536)
+        assert (x["grid"], x["chunks"], x["steps/wave"]) == (512, 64, 8)
+    assert b[0]["vecq"] and b[1]["vecq"] and not b[2]["vecq"]  # k is innermost in Y
+
+
+def test_manybody_takes_the_materialised_fallback():
+    for x in dry("ij,jk,ik->ijk", [19, 17, 13], [], 1.0, 0.0):
+        assert x["Q"] == "" and x["P"] == "ijk" and x["R"] == "materialised" and x["qi"] == "-"
+
+
+def test_tucker_lowering_and_precision_per_width():
+    b = dry("ia,jb,kc,abc->ijk", [512, 512, 128], [32, 32, 16], 1.0, -1.0, prec="bf16")
+    assert [x["L"] for x in b] == ["direct", "direct", "direct", "materialised"]
+    assert [x["KP"] for x in b] == [32, 32, 16, 32]
+    # BF16 contraction inputs only where the width is 32
+    assert [x["contract"] for x in b] == ["bf16", "bf16", "fp32", "bf16"]
+    assert b[3]["chain"] and b[3]["wave_rows"]          # core: 65,536 rows, 16 column steps
+    assert not any(x["wave_rows"] for x in b[:3])
+
+
+def test_tensor_train_and_icews_lowerings():
+    tt = dry("ia,jab,kbc,lc->ijkl", [128, 128, 96, 64], [16, 16, 16], 1.0, 0.0)
+    assert all(x["KP"] == 16 for x in tt)
+    assert sum(x["chain"] for x in tt) >= 2
+    ic = dry("ir,jr,ak,kr,tr->ijat", [249, 249, 20, 228], [32, 8], 1.0, 0.0)
+    assert ic[0]["P"] == "iat" and ic[0]["wave_rows"] and ic[0]["steps/wave"] == 8
+    assert ic[2]["R"] == "product(ir,jr)"
+
+
+def test_latent_only_operand_and_shared_letter():
+    b = dry("ir,jr,jkr->ijk", [21, 18, 20], [5], 1.0, 0.0)
+    assert len(b) == 3
+    b = dry("ia,jb,ab->ij", [30, 20], [4, 3], 1.0, 0.0)
+    assert b[2]["op"] == "ab"
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_geometry_invariants_on_random_cp(seed):
+    """For random CP shapes and ranks: the grid is panels x chunks, the chunks
+    cover every column step, and the padded width is the next of 16/32/64."""
+    rng = np.random.default_rng(seed)
+    dims = [int(v) for v in rng.integers(5, 300, size=3)]
+    R = int(rng.choice([3, 8, 16, 24, 32, 40, 64]))
+    for x in dry("ir,jr,kr->ijk", dims, [R], 1.0, 0.0):
+        assert x["KP"] == (16 if R <= 16 else 32 if R <= 32 else 64) and x["K"] == R
+        qstep = 32 if x["KP"] == 32 else 16
+        rows = {16: 64, 32: 128 if x["wave_rows"] else 32, 64: 16}[x["KP"]]
+        panels = math.ceil(x["nP"] / rows)
+        assert x["grid"] == panels * x["chunks"]
+        nqi = {"i": dims[0], "j": dims[1], "k": dims[2]}[x["qi"]]
+        n_steps = (x["nQ"] // nqi) * math.ceil(nqi / qstep)
+        split = 1 if x["wave_rows"] else 4
+        assert x["chunks"] * split * x["steps/wave"] >= n_steps
+        assert (x["chunks"] - 1) * split * x["steps/wave"] < n_steps
+
+
+def test_dry_run_reports_the_same_errors():
+    from paper_2602_02759_amd.nnef import NnefError, nnef_plan_dry
+    with pytest.raises(NnefError) as e:
+        nnef_plan_dry("ii,jr->ij", [4, 5], [3])
+    assert e.value.status == 1
+    with pytest.raises(NnefError) as e:
+        nnef_plan_dry("ir,jr->ij", [4, 5], [3], 0.0, 0.5)
+    assert e.value.status == 3
+    with pytest.raises(NnefError) as e:
+        nnef_plan_dry("ir,jr->ij", [4, 5], [3], family="negbin", family_param=-1.0)
+    assert e.value.status == 3
+    assert dry("ir,jr->ij", [4, 5], [3], family="js")
