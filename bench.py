@@ -156,7 +156,7 @@ def cpu_baseline(p, n_sweeps):
 
     from oracle import oracle as O
     f = [np.maximum(t, 1e-10).astype(np.float64) for t in p.init]
-    O.sweep(p.model_str, f, p.Y, p.M, p.alpha, p.beta, 1e-10)  # warm-up
+    first = O.sweep(p.model_str, f, p.Y, p.M, p.alpha, p.beta, 1e-10)  # warm-up
     t0 = time.perf_counter()
     for _ in range(n_sweeps):
         f = O.sweep(p.model_str, f, p.Y, p.M, p.alpha, p.beta, 1e-10)
@@ -164,7 +164,27 @@ def cpu_baseline(p, n_sweeps):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {"value": n_sweeps / dt, "unit": "sweeps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_sweeps} full FP64 sweeps of the same workload after 1 warm-up "
-                      f"({dt:.1f} s, numpy einsum on {os.cpu_count()} host CPUs)"}
+                      f"({dt:.1f} s, numpy einsum on {os.cpu_count()} host CPUs)"}, first
+
+
+def error_vs_oracle(p, Y, M, first):
+    """One GPU sweep from the seeded init per contraction precision vs the
+    oracle's FP64 sweep from the same init: max over factors of the relative
+    Frobenius error (the parity tests' measure, at the benchmark's full size)."""
+    import numpy as np
+    import torch
+
+    from paper_2602_02759_amd.nnef import Plan
+    res = {}
+    for prec in ("fp32", "bf16", "fp16"):
+        plan = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, prec=prec)
+        f = [torch.from_numpy(np.maximum(t, 1e-10)).to(Y.device) for t in p.init]
+        plan.step(Y, M, f, n_sweeps=1)
+        torch.cuda.synchronize()
+        res[prec] = max(float(np.linalg.norm(g.cpu().numpy().astype(np.float64) - r) / np.linalg.norm(r))
+                        for g, r in zip(f, first))
+    return {"measure": "max over factors of ||theta_gpu - theta_oracle||_F / ||theta_oracle||_F "
+                       "after one sweep from the seeded init", **res}
 
 
 TRAIN_HORIZON = 8
@@ -454,7 +474,8 @@ def main():
                         for k, r in res.items() if k != "plain_fp32"},
             "extrapolator_training": info}
     if args.cpu_sweeps > 0:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sweeps)
+        out["cpu_baseline"], first = cpu_baseline(p, args.cpu_sweeps)
+        out["error_vs_oracle"] = error_vs_oracle(p, Y, M, first)
     print(json.dumps(out), flush=True)
 
 
