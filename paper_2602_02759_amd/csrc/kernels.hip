@@ -62,11 +62,13 @@ __device__ __forceinline__ void colsum_body(const UpdateArgs& a, float* dcol) {
 
 __global__ __launch_bounds__(256) void colsum_kernel(UpdateArgs a, float* dcol) { colsum_body(a, dcol); }
 
-// One workgroup per 64 consecutive (p, k) outputs; its four waves sum
-// interleaved quarters of the partial slots, then wave 0 adds the quarters in a
-// fixed order (deterministic) and applies the update.
+// One workgroup of NW waves per 64 consecutive (p, k) outputs.  Wave w sums
+// the partial slots w, w + NW, w + 2 NW, ... with U independent running sums
+// (U loads in flight per lane for each of N and D), then wave 0 adds the waves'
+// sums in wave order (deterministic) and applies the update.
+template <int NW, int U>
 __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dcol, int blk) {
-  __shared__ double sN[4][64], sD[4][64];
+  __shared__ double sN[NW][64], sD[NW][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t n = (int64_t)a.nP * a.K;
   const int64_t idx = (int64_t)blk * 64 + lane;
@@ -74,34 +76,48 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dc
   const int p = valid ? (int)(idx / a.K) : 0, k = valid ? (int)(idx % a.K) : 0;
   double N = 0.0, D = 0.0;
   if (valid) {
-    // eight independent partial sums keep eight loads in flight per lane;
-    // they are combined in a fixed order (deterministic)
     const size_t stride = (size_t)a.nP * a.KP;
     const float* pn = a.partN + (size_t)p * a.KP + k;
     const float* pd = a.partD + (size_t)p * a.KP + k;
-    double sn[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int ch = w;
-    for (; ch + 28 < a.n_chunks; ch += 32) {
+    double sn[U], sd[U];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sn[j] += pn[(size_t)(ch + 4 * j) * stride];
+    for (int j = 0; j < U; ++j) sn[j] = sd[j] = 0.0;
+    int ch = w;
+    for (; ch + (U - 1) * NW < a.n_chunks; ch += U * NW) {
+#pragma unroll
+      for (int j = 0; j < U; ++j) sn[j] += pn[(size_t)(ch + NW * j) * stride];
       if (!a.no_d) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) sd[j] += pd[(size_t)(ch + 4 * j) * stride];
+        for (int j = 0; j < U; ++j) sd[j] += pd[(size_t)(ch + NW * j) * stride];
       }
     }
-    for (; ch < a.n_chunks; ch += 4) {
+    for (; ch < a.n_chunks; ch += NW) {
       sn[0] += pn[(size_t)ch * stride];
       if (!a.no_d) sd[0] += pd[(size_t)ch * stride];
     }
-    N = ((sn[0] + sn[1]) + (sn[2] + sn[3])) + ((sn[4] + sn[5]) + (sn[6] + sn[7]));
-    D = ((sd[0] + sd[1]) + (sd[2] + sd[3])) + ((sd[4] + sd[5]) + (sd[6] + sd[7]));
+    // pairwise in a fixed pattern
+#pragma unroll
+    for (int h = U / 2; h > 0; h /= 2)
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        sn[j] += sn[j + h];
+        sd[j] += sd[j + h];
+      }
+    N = sn[0];
+    D = sd[0];
   }
   sN[w][lane] = N;
   sD[w][lane] = D;
   __syncthreads();
   if (w == 0 && valid) {
-    N = ((sN[0][lane] + sN[1][lane]) + sN[2][lane]) + sN[3][lane];
-    D = a.no_d ? (double)dcol[k] : ((sD[0][lane] + sD[1][lane]) + sD[2][lane]) + sD[3][lane];
+    N = 0.0;
+    D = 0.0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      N += sN[j][lane];
+      D += sD[j][lane];
+    }
+    if (a.no_d) D = (double)dcol[k];
     if (a.theta) {
       float* th = a.theta + (size_t)p * a.ldT + k;
       *th = mu_rule(*th, (float)N, (float)D, a.upd, a.gamma, a.eps);
@@ -118,8 +134,10 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dc
   }
 }
 
-__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a, const float* dcol) {
-  update_body(a, dcol, blockIdx.x);
+// Single plans: sixteen waves per workgroup, so that at the usual 64 partial
+// slots every lane's loads are in flight at once.
+__global__ __launch_bounds__(1024) void update_kernel(UpdateArgs a, const float* dcol) {
+  update_body<16, 4>(a, dcol, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void colsum_batched(const UpdateArgs* __restrict__ args,
@@ -133,7 +151,7 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateArgs* __restri
   for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
     const WorkItem it = work[w];
     const UpdateArgs a = args[it.run];
-    update_body(a, a.dcol, it.blk);
+    update_body<4, 8>(a, a.dcol, it.blk);
     __syncthreads();
   }
 }
@@ -301,7 +319,7 @@ int launch_update(const UpdateArgs& a, float* dcol, void* stream) {
   }
   const int64_t n = (int64_t)a.nP * a.K;
   const int grid = (int)((n + 63) / 64);
-  hipLaunchKernelGGL(update_kernel, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, a, dcol);
+  hipLaunchKernelGGL(update_kernel, dim3(grid > 0 ? grid : 1), dim3(1024), 0, s, a, dcol);
   return (int)hipGetLastError();
 }
 
