@@ -123,3 +123,44 @@ def test_quarter_scale_batched_workload():
     b.step(Ys, Ms, facs, 1)
     torch.cuda.synchronize()
     _check_runs(runs, before, "quarter-scale")
+
+
+def test_full_size_batched_workload_sampled():
+    """The benchmark's launch configuration: all 96 CP4 problems at full size
+    (mode sizes U{32..160}) x 8 restarts in one autotuned batched plan, data
+    drawn on the GPU.  After one sweep of all 768 runs, the runs of the three
+    smallest problems (first and last restart) are checked against the
+    oracle's sweep from the same state; every run stays finite and positive."""
+    import torch
+    desc = datagen.cp4_batch_descriptors()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    Ys, runs, probs = [], [], []
+    for dims, R in desc:
+        fs = [torch._standard_gamma(torch.full((d, R), 0.5, device="cuda"), generator=gen) for d in dims]
+        lam = torch.einsum("ir,jr,kr,lr->ijkl", *fs).contiguous()
+        Ys.append(torch.poisson(lam, generator=gen).contiguous())
+        del lam, fs
+        for _ in range(8):
+            runs.append([torch._standard_gamma(torch.ones((d, R), device="cuda"), generator=gen).clamp_min(EPS)
+                         for d in dims])
+        probs.append(dict(model_str="ir,jr,kr,lr->ijkl", mode_sizes=dims, ranks=[R], alpha=1.0, beta=0.0,
+                          n_restarts=8, masked=False))
+    from paper_2602_02759_amd.nnef import Batch
+    b = Batch(probs, eps=EPS)
+    b.autotune(Ys, None, runs)
+    print(b.describe(), flush=True)
+    sizes = [int(np.prod(d)) for d, _ in desc]
+    picked = sorted(range(len(desc)), key=lambda i: sizes[i])[:3]
+    sample = [(i, r) for i in picked for r in (0, 7)]
+    before = {(i, r): [t.cpu().numpy() for t in runs[8 * i + r]] for i, r in sample}
+    b.step(Ys, None, runs, 1)
+    torch.cuda.synchronize()
+    for f in runs:
+        for t in f:
+            assert bool(torch.isfinite(t).all()) and bool((t >= EPS).all())
+    for i, r in sample:
+        Y = Ys[i].cpu().numpy().astype(np.float64)
+        ref = O.sweep("ir,jr,kr,lr->ijkl", [x.astype(np.float64) for x in before[(i, r)]], Y, None, 1.0, 0.0, EPS)
+        got = [t.cpu().numpy() for t in runs[8 * i + r]]
+        assert_step_parity(got, ref, TOL, f"problem {i} {desc[i]} restart {r}")
