@@ -34,9 +34,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--beta", type=float, default=1.0)
-    ap.add_argument("--workload", choices=("cp", "batched", "tucker", "tt", "uber", "uber400", "icews"),
+    ap.add_argument("--workload", choices=("cp", "batched", "nmf", "tucker", "tt", "uber", "uber400", "icews"),
                     default="cp",
-                    help="cp: the CP 256^3 headline; batched: 96 CP4 problems x 8 restarts; "
+                    help="cp: the CP 256^3 headline; batched: 96 CP4 problems x 8 restarts; nmf: 200x150 R=8 KL; "
                          "tucker / tt: the Tucker IS and tensor-train workloads; uber / uber400 / icews: "
                          "the paper's custom strings at its data shapes (synthetic counts)")
     ap.add_argument("--n", type=int, default=256, help="mode size")
@@ -287,16 +287,17 @@ def bench_batched(args):
 
 
 def bench_single(args):
-    """One of the secondary workloads (Tucker 512x512x128 IS, tensor train
-    128x128x96x64 KL, the Uber and ICEWS strings at the paper's shapes): plain
-    FP32 and BF16-contraction sweeps/s, and time to the plain run's 200-sweep
+    """One of the secondary workloads (NMF 200x150 R=8 KL, Tucker 512x512x128
+    IS, tensor train 128x128x96x64 KL, the Uber and ICEWS strings at the
+    paper's shapes): plain FP32 and BF16-contraction sweeps/s, eager and
+    replayed from a captured graph, and time to the plain run's 200-sweep
     loss."""
     import numpy as np
     import torch
 
     from paper_2602_02759_amd import datagen
     from paper_2602_02759_amd.nnef import Plan
-    p = {"tucker": datagen.tucker3, "tt": datagen.tt4, "uber": datagen.uber_problem,
+    p = {"nmf": datagen.nmf_kl, "tucker": datagen.tucker3, "tt": datagen.tt4, "uber": datagen.uber_problem,
          "uber400": lambda: datagen.uber_problem(mesh=400), "icews": datagen.icews_problem}[args.workload]()
     Y = torch.from_numpy(p.Y).cuda()
     M = torch.from_numpy(p.M).cuda() if p.M is not None else None
@@ -316,8 +317,22 @@ def bench_single(args):
         torch.cuda.synchronize()
         n_pass, pass_ms = plan.timing()
         plan.set_timing(False)
+        # the same sweeps captured once in a graph and replayed (removes the host
+        # launch cost, which bounds small problems)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.step(Y, M, f, n_sweeps=args.steps)
+        g.replay()
+        torch.cuda.synchronize()
+        ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev2.record()
+        g.replay()
+        ev3.record()
+        torch.cuda.synchronize()
         res[prec] = {"sweeps_per_s": 1e3 * args.steps / ev0.elapsed_time(ev1),
+                     "graph_sweeps_per_s": 1e3 * args.steps / ev2.elapsed_time(ev3),
                      "avg_fused_pass_us": 1e3 * pass_ms / max(n_pass, 1), "lowering": plan.describe()}
+        del g
     # time to the plain FP32 run's own loss after 200 sweeps, for the plain,
     # BF16 and learned forms (the extrapolator is trained on NMF, CP and Tucker
     # trajectories drawn with other seeds)
