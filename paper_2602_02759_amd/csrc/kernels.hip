@@ -126,7 +126,7 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dc
       a.DL[idx] = (float)D;
     }
   }
-  if (a.loss_out && blk == 0 && w == 1) {
+  if (a.loss_out && blk == 0 && w == (NW > 1 ? 1 : 0)) {
     double sl = 0.0;
     for (int i = lane; i < a.n_loss_part; i += 64) sl += a.loss_part[i];
     sl = wave_sum(sl);
@@ -134,10 +134,12 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dc
   }
 }
 
-// Single plans: sixteen waves per workgroup, so that at the usual 64 partial
-// slots every lane's loads are in flight at once.
-__global__ __launch_bounds__(1024) void update_kernel(UpdateArgs a, const float* dcol) {
-  update_body<16, 4>(a, dcol, blockIdx.x);
+// Single plans: the waves per workgroup follow the number of partial slots,
+// so that every lane's loads are in flight at once (sixteen waves at the usual
+// 64 slots) and blocks with few slots (many rows) do not idle waves.
+template <int NW, int U>
+__global__ __launch_bounds__(64 * NW) void update_kernel(UpdateArgs a, const float* dcol) {
+  update_body<NW, U>(a, dcol, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void colsum_batched(const UpdateArgs* __restrict__ args,
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
 // lanes' sums with a fixed butterfly (deterministic).  Used when there are
 // few outputs with long sums, where one thread per output leaves the chip
 // idle and every thread waits on one load per term.
-template <int NIN>
+template <int NIN, bool ONE_SUM>
 __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log2g, uint32_t n_sum) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int G = 1 << log2g;
@@ -237,13 +239,18 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
           int64_t so[NIN];
 #pragma unroll
           for (int i = 0; i < NIN; ++i) so[i] = off[i];
-          uint32_t rem = c;
-          for (int d = a.n_sum - 1; d >= 0; --d) {
-            const uint32_t sz = (uint32_t)a.sum_size[d];
-            const uint32_t v = rem % sz;
-            rem /= sz;
+          if constexpr (ONE_SUM) {  // one summed letter: its index is c itself
 #pragma unroll
-            for (int i = 0; i < NIN; ++i) so[i] += (int64_t)v * a.in_sum_stride[i][d];
+            for (int i = 0; i < NIN; ++i) so[i] += (int64_t)c * a.in_sum_stride[i][0];
+          } else {
+            uint32_t rem = c;
+            for (int d = a.n_sum - 1; d >= 0; --d) {
+              const uint32_t sz = (uint32_t)a.sum_size[d];
+              const uint32_t v = rem % sz;
+              rem /= sz;
+#pragma unroll
+              for (int i = 0; i < NIN; ++i) so[i] += (int64_t)v * a.in_sum_stride[i][d];
+            }
           }
           float pr = 1.f;
 #pragma unroll
@@ -319,7 +326,13 @@ int launch_update(const UpdateArgs& a, float* dcol, void* stream) {
   }
   const int64_t n = (int64_t)a.nP * a.K;
   const int grid = (int)((n + 63) / 64);
-  hipLaunchKernelGGL(update_kernel, dim3(grid > 0 ? grid : 1), dim3(1024), 0, s, a, dcol);
+  const dim3 g(grid > 0 ? grid : 1);
+  if (a.n_chunks >= 32)
+    hipLaunchKernelGGL((update_kernel<16, 4>), g, dim3(1024), 0, s, a, dcol);
+  else if (a.n_chunks >= 4)
+    hipLaunchKernelGGL((update_kernel<4, 8>), g, dim3(256), 0, s, a, dcol);
+  else
+    hipLaunchKernelGGL((update_kernel<1, 4>), g, dim3(64), 0, s, a, dcol);
   return (int)hipGetLastError();
 }
 
@@ -330,6 +343,14 @@ int launch_update_batched(const UpdateArgs* args, const int* colsum_runs, int n_
   if (n_colsum > 0) hipLaunchKernelGGL(colsum_batched, dim3(n_colsum), dim3(256), 0, s, args, colsum_runs);
   if (n_work > 0) hipLaunchKernelGGL(update_batched, dim3(grid), dim3(256), 0, s, args, work, n_work);
   return (int)hipGetLastError();
+}
+
+template <int NIN>
+void launch_split(const EinsumArgs& a, dim3 grid, int log2g, uint32_t n_sum, hipStream_t s) {
+  if (a.n_sum == 1)
+    hipLaunchKernelGGL((einsum_split_kernel<NIN, true>), grid, dim3(256), 0, s, a, log2g, n_sum);
+  else
+    hipLaunchKernelGGL((einsum_split_kernel<NIN, false>), grid, dim3(256), 0, s, a, log2g, n_sum);
 }
 
 int launch_einsum(const EinsumArgs& a, void* stream) {
@@ -345,10 +366,10 @@ int launch_einsum(const EinsumArgs& a, void* stream) {
     const dim3 grid((unsigned)((threads + 255) / 256));
     hipStream_t s = (hipStream_t)stream;
     switch (a.n_in) {
-      case 1: hipLaunchKernelGGL(einsum_split_kernel<1>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
-      case 2: hipLaunchKernelGGL(einsum_split_kernel<2>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
-      case 3: hipLaunchKernelGGL(einsum_split_kernel<3>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
-      default: hipLaunchKernelGGL(einsum_split_kernel<4>, grid, dim3(256), 0, s, a, log2g, (uint32_t)n_sum); break;
+      case 1: launch_split<1>(a, grid, log2g, (uint32_t)n_sum, s); break;
+      case 2: launch_split<2>(a, grid, log2g, (uint32_t)n_sum, s); break;
+      case 3: launch_split<3>(a, grid, log2g, (uint32_t)n_sum, s); break;
+      default: launch_split<4>(a, grid, log2g, (uint32_t)n_sum, s); break;
     }
     return (int)hipGetLastError();
   }
