@@ -210,6 +210,14 @@ std::vector<Step> plan_contraction(const Model& m, std::vector<TensorRef> in, co
           best_subs = subs;
         }
       }
+    // letters of the intermediate: those summed later first, then the final
+    // output's letters in its order, so that the intermediate's fastest index
+    // is the output's fastest one and the next step reads it coalesced
+    std::stable_sort(best_subs.begin(), best_subs.end(), [&](char x, char y) {
+      const size_t px = out.subs.find(x), py = out.subs.find(y);
+      const long kx = px == std::string::npos ? -1 : (long)px, ky = py == std::string::npos ? -1 : (long)py;
+      return kx < ky;
+    });
     TensorRef tmp;
     tmp.kind = TK_WS;
     tmp.id = (int)ws_sizes.size();
