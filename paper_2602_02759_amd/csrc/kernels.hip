@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <cstdint>
 #include <cmath>
 
 #include "nnef_internal.hpp"
@@ -218,17 +219,63 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
   for (int i = 0; i < NIN; ++i) off[i] = 0;
   int64_t ooff = 0;
   if (valid) {
-    int64_t rem = o;
-    for (int d = a.n_out - 1; d >= 0; --d) {
-      const int64_t v = rem % a.out_size[d];
-      rem /= a.out_size[d];
-      ooff += v * a.out_stride[d];
+    if (a.n_out_total <= (int64_t)UINT32_MAX) {  // 32-bit division where it suffices
+      uint32_t rem = (uint32_t)o;
+      for (int d = a.n_out - 1; d >= 0; --d) {
+        const uint32_t sz = (uint32_t)a.out_size[d];
+        const int64_t v = (int64_t)(rem % sz);
+        rem /= sz;
+        ooff += v * a.out_stride[d];
 #pragma unroll
-      for (int i = 0; i < NIN; ++i) off[i] += v * a.in_out_stride[i][d];
+        for (int i = 0; i < NIN; ++i) off[i] += v * a.in_out_stride[i][d];
+      }
+    } else {
+      int64_t rem = o;
+      for (int d = a.n_out - 1; d >= 0; --d) {
+        const int64_t v = rem % a.out_size[d];
+        rem /= a.out_size[d];
+        ooff += v * a.out_stride[d];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) off[i] += v * a.in_out_stride[i][d];
+      }
     }
   }
   double acc = 0.0;
-  if (valid) {
+  if constexpr (ONE_SUM) {
+    // one summed letter: walk each input with a pointer step per term
+    if (valid) {
+      const float* ptr[NIN];
+      int64_t step[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) {
+        const int64_t st = a.in_sum_stride[i][0];
+        ptr[i] = a.in[i] + off[i] + (int64_t)g * st;
+        step[i] = (int64_t)G * st;
+      }
+      uint32_t c = g;
+      for (; c + 3u * (uint32_t)G < n_sum; c += 4u * (uint32_t)G) {
+        float pr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          pr[u] = 1.f;
+#pragma unroll
+          for (int i = 0; i < NIN; ++i) pr[u] *= ptr[i][u * step[i]];
+        }
+        acc += ((double)pr[0] + (double)pr[1]) + ((double)pr[2] + (double)pr[3]);
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) ptr[i] += 4 * step[i];
+      }
+      for (; c < n_sum; c += (uint32_t)G) {
+        float pr = 1.f;
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+          pr *= ptr[i][0];
+          ptr[i] += step[i];
+        }
+        acc += (double)pr;
+      }
+    }
+  } else if (valid) {
     for (uint32_t c0 = g; c0 < n_sum; c0 += 4u * (uint32_t)G) {
       float prod[4];
 #pragma unroll
@@ -239,18 +286,13 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
           int64_t so[NIN];
 #pragma unroll
           for (int i = 0; i < NIN; ++i) so[i] = off[i];
-          if constexpr (ONE_SUM) {  // one summed letter: its index is c itself
+          uint32_t rem = c;
+          for (int d = a.n_sum - 1; d >= 0; --d) {
+            const uint32_t sz = (uint32_t)a.sum_size[d];
+            const uint32_t v = rem % sz;
+            rem /= sz;
 #pragma unroll
-            for (int i = 0; i < NIN; ++i) so[i] += (int64_t)c * a.in_sum_stride[i][0];
-          } else {
-            uint32_t rem = c;
-            for (int d = a.n_sum - 1; d >= 0; --d) {
-              const uint32_t sz = (uint32_t)a.sum_size[d];
-              const uint32_t v = rem % sz;
-              rem /= sz;
-#pragma unroll
-              for (int i = 0; i < NIN; ++i) so[i] += (int64_t)v * a.in_sum_stride[i][d];
-            }
+            for (int i = 0; i < NIN; ++i) so[i] += (int64_t)v * a.in_sum_stride[i][d];
           }
           float pr = 1.f;
 #pragma unroll
