@@ -387,6 +387,141 @@ int launch_update_batched(const UpdateArgs* args, const int* colsum_runs, int n_
   return (int)hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// A two-input contraction with one summed letter k, written as a batched
+// matrix product out[b][m][n] = sum_k X[b][m][k] Y[b][k][n]: output letters
+// found only in X form the row index m, those only in Y the column index n,
+// those in both the batch index b (each a row-major combination of its
+// letters, in output order).  One wave computes a 32 x 32 tile of one batch on
+// v_mfma_f32_32x32x2_f32 (FP32 accumulate); lane l = 32 g + c supplies
+// A[row c][k g] and B[k g][col c], and accumulator register v holds
+// C[row 8(v/4) + 4g + v%4][col c].
+struct GemmGroup {
+  int n;                               // letters in the group
+  int64_t size[kMaxEinsumLetters];
+  int64_t sx[kMaxEinsumLetters];       // stride in X (0 when absent)
+  int64_t sy[kMaxEinsumLetters];       // stride in Y
+  int64_t so[kMaxEinsumLetters];       // stride in the output
+};
+
+struct GemmArgs {
+  const float* X;
+  const float* Y;
+  float* out;
+  GemmGroup gm, gn, gb;
+  int64_t M, N, B, K;
+  int64_t kx, ky;                      // strides of the summed letter in X and Y
+  int64_t tiles_m, tiles_n;
+};
+
+struct Off3 {
+  int64_t x, y, o;
+};
+
+__device__ __forceinline__ Off3 group_offsets(const GemmGroup& g, int64_t idx) {
+  Off3 r{0, 0, 0};
+  for (int d = g.n - 1; d >= 0; --d) {
+    const int64_t v = idx % g.size[d];
+    idx /= g.size[d];
+    r.x += v * g.sx[d];
+    r.y += v * g.sy[d];
+    r.o += v * g.so[d];
+  }
+  return r;
+}
+
+__global__ __launch_bounds__(256) void einsum_gemm_kernel(GemmArgs a) {
+  typedef float f16v __attribute__((ext_vector_type(16)));
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t n_tiles = a.tiles_m * a.tiles_n * a.B;
+  if (w >= n_tiles) return;  // whole waves only; no barrier follows
+  const int g = lane >> 5, c = lane & 31;
+  const int64_t tn = w % a.tiles_n, tm = (w / a.tiles_n) % a.tiles_m, bb = w / (a.tiles_n * a.tiles_m);
+  const int64_t m = tm * 32 + c, n = tn * 32 + c;
+  const bool mv = m < a.M, nv = n < a.N;
+  const Off3 ob = group_offsets(a.gb, bb);
+  const Off3 om = group_offsets(a.gm, mv ? m : 0);
+  const Off3 on = group_offsets(a.gn, nv ? n : 0);
+  const float* xp = a.X + ob.x + om.x + (int64_t)g * a.kx;
+  const float* yp = a.Y + ob.y + on.y + (int64_t)g * a.ky;
+  const int64_t kx2 = 2 * a.kx, ky2 = 2 * a.ky;
+  f16v acc = {};
+  int64_t k0 = 0;
+  for (; k0 + 16 <= a.K; k0 += 16) {  // eight steps with every load issued first
+    float av[8], bv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      av[j] = mv ? xp[j * kx2] : 0.f;
+      bv[j] = nv ? yp[j * ky2] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], acc, 0, 0, 0);
+    xp += 8 * kx2;
+    yp += 8 * ky2;
+  }
+  for (; k0 < a.K; k0 += 2) {
+    const bool kv = k0 + g < a.K;
+    const float av = (mv && kv) ? xp[0] : 0.f;
+    const float bv = (nv && kv) ? yp[0] : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    xp += kx2;
+    yp += ky2;
+  }
+  // rows of this lane's accumulator registers: their output offsets come from
+  // the lanes that own those rows (every lane takes part in the shuffles)
+  const int64_t base = ob.o + on.o;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int r = 8 * (v >> 2) + 4 * g + (v & 3);
+    const int lo = __shfl((int)(uint32_t)om.o, r, 64);
+    const int hi = __shfl((int)(uint32_t)((uint64_t)om.o >> 32), r, 64);
+    const int64_t rowo = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    if (nv && tm * 32 + r < a.M) a.out[base + rowo] = acc[v];
+  }
+}
+
+// Classify the letters of a two-input, one-summed-letter step; false when
+// the step does not have that form (or an output letter is in neither input).
+bool gemm_args(const EinsumArgs& e, GemmArgs& g) {
+  if (e.n_in != 2 || e.n_sum != 1) return false;
+  g.X = e.in[0];
+  g.Y = e.in[1];
+  g.out = e.out;
+  g.gm.n = g.gn.n = g.gb.n = 0;
+  g.M = g.N = g.B = 1;
+  for (int d = 0; d < e.n_out; ++d) {
+    const int64_t sx = e.in_out_stride[0][d], sy = e.in_out_stride[1][d];
+    GemmGroup* grp;
+    int64_t* tot;
+    if (sx != 0 && sy == 0) {
+      grp = &g.gm;
+      tot = &g.M;
+    } else if (sx == 0 && sy != 0) {
+      grp = &g.gn;
+      tot = &g.N;
+    } else if (sx != 0 && sy != 0) {
+      grp = &g.gb;
+      tot = &g.B;
+    } else {
+      if (e.out_size[d] != 1) return false;
+      continue;  // a size-1 letter adds nothing
+    }
+    const int i = grp->n++;
+    grp->size[i] = e.out_size[d];
+    grp->sx[i] = sx;
+    grp->sy[i] = sy;
+    grp->so[i] = e.out_stride[d];
+    *tot *= e.out_size[d];
+  }
+  g.K = e.sum_size[0];
+  g.kx = e.in_sum_stride[0][0];
+  g.ky = e.in_sum_stride[1][0];
+  g.tiles_m = (g.M + 31) / 32;
+  g.tiles_n = (g.N + 31) / 32;
+  return true;
+}
+
 template <int NIN>
 void launch_split(const EinsumArgs& a, dim3 grid, int log2g, uint32_t n_sum, hipStream_t s) {
   if (a.n_sum == 1)
@@ -399,6 +534,15 @@ int launch_einsum(const EinsumArgs& a, void* stream) {
   if (a.n_out_total <= 0) return 0;
   int64_t n_sum = 1;
   for (int d = 0; d < a.n_sum; ++d) n_sum *= a.sum_size[d];
+  GemmArgs ga;
+  if (gemm_args(a, ga) && ga.M >= 8 && ga.N >= 8 && ga.M * ga.N * ga.B * ga.K >= (int64_t(1) << 20)) {
+    const int64_t waves = ga.tiles_m * ga.tiles_n * ga.B;
+    if ((waves + 3) / 4 < (int64_t(1) << 31)) {
+      hipLaunchKernelGGL(einsum_gemm_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
+                         (hipStream_t)stream, ga);
+      return (int)hipGetLastError();
+    }
+  }
   if (n_sum >= 16 && n_sum < (int64_t(1) << 31) && a.n_in >= 1 && a.n_in <= 4) {
     // lanes per output: enough threads to fill the chip, at most 64
     int log2g = 0;
