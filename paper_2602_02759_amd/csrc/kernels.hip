@@ -171,16 +171,42 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   if (i < a.n) a.theta[i] = mu_rule(a.theta[i], a.N[i], a.D[i], a.upd, a.gamma, a.eps);
 }
 
+// One thread per output; NIN inputs (loops over inputs unrolled, offsets in
+// registers).  With no summed letter the output is a plain product.
+template <int NIN>
 __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= a.n_out_total) return;
-  int64_t off[kMaxEinsumIn] = {0, 0, 0, 0};
-  int64_t ooff = 0, rem = o;
-  for (int d = a.n_out - 1; d >= 0; --d) {
-    const int64_t v = rem % a.out_size[d];
-    rem /= a.out_size[d];
-    ooff += v * a.out_stride[d];
-    for (int i = 0; i < a.n_in; ++i) off[i] += v * a.in_out_stride[i][d];
+  int64_t off[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) off[i] = 0;
+  int64_t ooff = 0;
+  if (a.n_out_total <= (int64_t)UINT32_MAX) {  // 32-bit division where it suffices
+    uint32_t rem = (uint32_t)o;
+    for (int d = a.n_out - 1; d >= 0; --d) {
+      const uint32_t sz = (uint32_t)a.out_size[d];
+      const int64_t v = (int64_t)(rem % sz);
+      rem /= sz;
+      ooff += v * a.out_stride[d];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) off[i] += v * a.in_out_stride[i][d];
+    }
+  } else {
+    int64_t rem = o;
+    for (int d = a.n_out - 1; d >= 0; --d) {
+      const int64_t v = rem % a.out_size[d];
+      rem /= a.out_size[d];
+      ooff += v * a.out_stride[d];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) off[i] += v * a.in_out_stride[i][d];
+    }
+  }
+  if (a.n_sum == 0) {
+    float prod = 1.f;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) prod *= a.in[i][off[i]];
+    a.out[ooff] = prod;
+    return;
   }
   int64_t n_sum = 1;
   for (int d = 0; d < a.n_sum; ++d) n_sum *= a.sum_size[d];
@@ -188,13 +214,16 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
   double acc = 0.0;
   for (int64_t cidx = 0; cidx < n_sum; ++cidx) {
     float prod = 1.f;
-    for (int i = 0; i < a.n_in; ++i) prod *= a.in[i][off[i]];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) prod *= a.in[i][off[i]];
     acc += (double)prod;
     for (int d = a.n_sum - 1; d >= 0; --d) {
       ++cnt[d];
-      for (int i = 0; i < a.n_in; ++i) off[i] += a.in_sum_stride[i][d];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) off[i] += a.in_sum_stride[i][d];
       if (cnt[d] < a.sum_size[d]) break;
-      for (int i = 0; i < a.n_in; ++i) off[i] -= a.sum_size[d] * a.in_sum_stride[i][d];
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) off[i] -= a.sum_size[d] * a.in_sum_stride[i][d];
       cnt[d] = 0;
     }
   }
@@ -530,7 +559,33 @@ void launch_split(const EinsumArgs& a, dim3 grid, int log2g, uint32_t n_sum, hip
     hipLaunchKernelGGL((einsum_split_kernel<NIN, false>), grid, dim3(256), 0, s, a, log2g, n_sum);
 }
 
-int launch_einsum(const EinsumArgs& a, void* stream) {
+// Two summed letters d, e whose strides satisfy stride(d) = size(e) * stride(e)
+// in every input are one letter of size size(d) * size(e) and stride stride(e).
+static EinsumArgs merge_sum_letters(EinsumArgs a) {
+  bool merged = true;
+  while (merged && a.n_sum > 1) {
+    merged = false;
+    for (int d = 0; d < a.n_sum && !merged; ++d)
+      for (int e = 0; e < a.n_sum && !merged; ++e) {
+        if (d == e) continue;
+        bool ok = true;
+        for (int i = 0; i < a.n_in; ++i)
+          ok = ok && a.in_sum_stride[i][d] == a.sum_size[e] * a.in_sum_stride[i][e];
+        if (!ok) continue;
+        a.sum_size[e] *= a.sum_size[d];  // letter e now spans both; d is removed
+        for (int j = d; j + 1 < a.n_sum; ++j) {
+          a.sum_size[j] = a.sum_size[j + 1];
+          for (int i = 0; i < a.n_in; ++i) a.in_sum_stride[i][j] = a.in_sum_stride[i][j + 1];
+        }
+        --a.n_sum;
+        merged = true;
+      }
+  }
+  return a;
+}
+
+int launch_einsum(const EinsumArgs& a_in, void* stream) {
+  const EinsumArgs a = merge_sum_letters(a_in);
   if (a.n_out_total <= 0) return 0;
   int64_t n_sum = 1;
   for (int d = 0; d < a.n_sum; ++d) n_sum *= a.sum_size[d];
@@ -559,8 +614,14 @@ int launch_einsum(const EinsumArgs& a, void* stream) {
     }
     return (int)hipGetLastError();
   }
-  const int64_t grid = (a.n_out_total + 255) / 256;
-  hipLaunchKernelGGL(einsum_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, a);
+  const dim3 grid((unsigned)((a.n_out_total + 255) / 256));
+  hipStream_t s = (hipStream_t)stream;
+  switch (a.n_in) {
+    case 1: hipLaunchKernelGGL(einsum_kernel<1>, grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(einsum_kernel<2>, grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(einsum_kernel<3>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(einsum_kernel<4>, grid, dim3(256), 0, s, a); break;
+  }
   return (int)hipGetLastError();
 }
 
