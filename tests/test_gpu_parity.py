@@ -81,6 +81,18 @@ def _case(name):
     if name == "shared_letter":  # column-side pieces 'jr' and 'jkr' share j
         return datagen.poisson_problem("shl", "ir,jr,jkr->ijk", dict(i=21, j=18, k=20, r=5),
                                        1.0, 0.0, seed=67, truth_shape=0.5)
+    if name == "lr_tucker":  # Tucker with a CP-factored core (eq. core_decomp): latent-only operands
+        return datagen.poisson_problem("lrt", "ia,jb,kc,ar,br,cr->ijk",
+                                       dict(i=30, j=26, k=22, a=8, b=6, c=5, r=4), 1.0, 0.0, seed=70,
+                                       truth_shape=0.5, missing=0.1)
+    if name == "lr_tucker_w32":
+        return datagen.gamma_noise_problem("lrt32", "ia,jb,kc,ar,br,cr->ijk",
+                                           dict(i=48, j=40, k=36, a=16, b=16, c=8, r=32), 1.0, -1.0,
+                                           seed=72, missing=0.1)
+    if name == "wits":  # the paper's trade-data string, positive continuous data, beta = -0.5
+        return datagen.gamma_noise_problem("wits", "er,ir,gr,tk,kr->eigt",
+                                           dict(e=20, i=18, g=12, t=7, r=6, k=2), 1.0, -0.5, seed=71,
+                                           missing=0.1)
     if name == "rkl":
         return datagen.gamma_noise_problem("rkl", "ir,jr,kr->ijk", dict(i=20, j=24, k=18, r=6),
                                            0.0, 1.0, seed=64, missing=0.2)
@@ -95,7 +107,8 @@ def _case(name):
 
 SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_gen", "tucker_small",
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
-         "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full"]
+         "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full",
+         "lr_tucker", "lr_tucker_w32", "wits"]
 
 
 @pytest.mark.parametrize("name", SMALL)

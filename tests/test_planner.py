@@ -75,6 +75,21 @@ def test_latent_only_operand_and_shared_letter():
     assert b[2]["op"] == "ab"
 
 
+def test_low_rank_tucker_and_wits_lowerings():
+    # Tucker with a CP-factored core: every block contracts over the core's CP
+    # rank r, including the latent-only operands ar, br, cr
+    b = dry("ia,jb,kc,ar,br,cr->ijk", [512, 512, 128], [32, 32, 16, 8], 1.0, -1.0)
+    assert [x["op"] for x in b] == ["ia", "jb", "kc", "ar", "br", "cr"]
+    assert all(x["kappa"] == "r" and x["K"] == 8 and x["KP"] == 16 for x in b)
+    assert all(x["chain"] for x in b)
+    # the paper's trade-data string: rank-32 CP with a rank-4 time factor
+    b = dry("er,ir,gr,tk,kr->eigt", [196, 196, 96, 29], [32, 4], 1.0, -0.5)
+    assert [x["op"] for x in b] == ["er", "ir", "gr", "tk", "kr"]
+    assert all(x["kappa"] == "r" and x["K"] == 32 for x in b)
+    for x in b:
+        assert x["nP"] * x["nQ"] == 196 * 196 * 96 * 29
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_geometry_invariants_on_random_cp(seed):
     """For random CP shapes and ranks: the grid is panels x chunks, the chunks
