@@ -66,6 +66,20 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   __shared__ double lred[4];
   float* red = reinterpret_cast<float*>(lds4);
 
+  // Every argument the prologue reads, requested in one batch: left to
+  // themselves the scalar loads follow the control flow below, one
+  // round trip to cold caches at a time, before the first data move.
+  {
+    const int i0 = a.xcd_remap, i1 = a.n_wg, i2 = a.n_panels, i3 = a.wave_rows, i4 = a.steps_per_wave,
+              i5 = a.nqis, i6 = a.nP, i7 = a.masked, i8 = a.nouter, i9 = a.K, i10 = a.ldL, i11 = a.ld_out[0];
+    const int64_t l0 = a.n_steps;
+    const void *p0 = a.Y, *p1 = a.p_off, *p2 = a.qo_yoff, *p3 = a.in_base, *p4 = a.inner, *p5 = a.outer[0],
+               *p6 = a.orow[0], *p7 = a.L;
+    __asm__ volatile("" ::"s"(i0), "s"(i1), "s"(i2), "s"(i3), "s"(i4), "s"(i5), "s"(i6), "s"(i7), "s"(i8), "s"(i9),
+                     "s"(i10), "s"(i11), "s"(l0), "s"(p0), "s"(p1), "s"(p2), "s"(p3), "s"(p4), "s"(p5), "s"(p6),
+                     "s"(p7));
+  }
+
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 5, c = lane & 31;
