@@ -5,6 +5,7 @@
 // einsum  - generic small contraction for side operands and chain-back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cstdint>
 #include <cmath>
@@ -141,6 +142,38 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dc
 template <int NW, int U>
 __global__ __launch_bounds__(64 * NW) void update_kernel(UpdateArgs a, const float* dcol) {
   update_body<NW, U>(a, dcol, blockIdx.x);
+}
+
+// Few partial slots (blocks with many rows): one output per thread, the slots
+// summed in slot order; the first workgroup's first wave also finishes the
+// loss.
+__global__ __launch_bounds__(256) void update_flat_kernel(UpdateArgs a, const float* dcol) {
+  const int64_t n = (int64_t)a.nP * a.K;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx < n) {
+    const int p = (int)(idx / a.K), k = (int)(idx % a.K);
+    const size_t stride = (size_t)a.nP * a.KP;
+    const size_t o = (size_t)p * a.KP + k;
+    double N = 0.0, D = 0.0;
+    for (int ch = 0; ch < a.n_chunks; ++ch) {
+      N += a.partN[(size_t)ch * stride + o];
+      if (!a.no_d) D += a.partD[(size_t)ch * stride + o];
+    }
+    if (a.no_d) D = (double)dcol[k];
+    if (a.theta) {
+      float* th = a.theta + (size_t)p * a.ldT + k;
+      *th = mu_rule(*th, (float)N, (float)D, a.upd, a.gamma, a.eps);
+    } else {
+      a.NL[idx] = (float)N;
+      a.DL[idx] = (float)D;
+    }
+  }
+  if (a.loss_out && blockIdx.x == 0 && threadIdx.x < 64) {
+    double sl = 0.0;
+    for (int i = (int)threadIdx.x; i < a.n_loss_part; i += 64) sl += a.loss_part[i];
+    sl = wave_sum(sl);
+    if (threadIdx.x == 0) *a.loss_out = sl;
+  }
 }
 
 __global__ __launch_bounds__(256) void colsum_batched(const UpdateArgs* __restrict__ args,
@@ -403,7 +436,8 @@ int launch_update(const UpdateArgs& a, float* dcol, void* stream) {
   else if (a.n_chunks >= 4)
     hipLaunchKernelGGL((update_kernel<4, 8>), g, dim3(256), 0, s, a, dcol);
   else
-    hipLaunchKernelGGL((update_kernel<1, 4>), g, dim3(64), 0, s, a, dcol);
+    hipLaunchKernelGGL(update_flat_kernel, dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)), dim3(256), 0, s, a,
+                       dcol);
   return (int)hipGetLastError();
 }
 
