@@ -242,7 +242,7 @@ def test_trained_network_gains():
     assert l1[-50:].mean() < 0.7 * l1[:10].mean()
 
     # held-out problems; MU is non-convex, so a proposal can move a run into a
-    # different basin: the gain is judged over several problems
+    # different basin: the gain is assessed over several problems
     wins, speedups = 0, []
     for seed in (43, 44, 45, 46, 47):
         p = datagen.cp3(1.0, 1.0, sizes=dict(i=64, j=56, k=48), R=16, seed=seed)
