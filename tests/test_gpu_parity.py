@@ -93,6 +93,10 @@ def _case(name):
         return datagen.gamma_noise_problem("wits", "er,ir,gr,tk,kr->eigt",
                                            dict(e=20, i=18, g=12, t=7, r=6, k=2), 1.0, -0.5, seed=71,
                                            missing=0.1)
+    if name == "batched_side_gemm":  # side and chain-back steps take the batched-MFMA form: batch letter r,
+        # ragged row and column counts (100, 9), an odd summed length (9)
+        return datagen.poisson_problem("bsg", "wr,irk,jrk->wij", dict(w=6, i=100, j=100, r=12, k=9), 1.0, 0.0,
+                                       seed=73, truth_shape=0.5, missing=0.1)
     if name == "rkl":
         return datagen.gamma_noise_problem("rkl", "ir,jr,kr->ijk", dict(i=20, j=24, k=18, r=6),
                                            0.0, 1.0, seed=64, missing=0.2)
@@ -108,7 +112,7 @@ def _case(name):
 SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_gen", "tucker_small",
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
          "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full",
-         "lr_tucker", "lr_tucker_w32", "wits"]
+         "lr_tucker", "lr_tucker_w32", "wits", "batched_side_gemm"]
 
 
 @pytest.mark.parametrize("name", SMALL)
