@@ -493,12 +493,17 @@ __device__ __forceinline__ Off3 group_offsets(const GemmGroup& g, int64_t idx) {
   return r;
 }
 
+// SPLIT: few tiles and a long sum.  The four waves of a workgroup take the
+// same tile and a quarter of k each; wave 0 adds the other waves' sums in wave
+// order (deterministic) and stores the tile.
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void einsum_gemm_kernel(GemmArgs a) {
   typedef float f16v __attribute__((ext_vector_type(16)));
   const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  const int64_t w = SPLIT ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wv;
   const int64_t n_tiles = a.tiles_m * a.tiles_n * a.B;
-  if (w >= n_tiles) return;  // whole waves only; no barrier follows
+  if (w >= n_tiles) return;  // whole waves (whole workgroups when SPLIT), before any barrier
   const int g = lane >> 5, c = lane & 31;
   const int64_t tn = w % a.tiles_n, tm = (w / a.tiles_n) % a.tiles_m, bb = w / (a.tiles_n * a.tiles_m);
   const int64_t m = tm * 32 + c, n = tn * 32 + c;
@@ -506,12 +511,18 @@ __global__ __launch_bounds__(256) void einsum_gemm_kernel(GemmArgs a) {
   const Off3 ob = group_offsets(a.gb, bb);
   const Off3 om = group_offsets(a.gm, mv ? m : 0);
   const Off3 on = group_offsets(a.gn, nv ? n : 0);
-  const float* xp = a.X + ob.x + om.x + (int64_t)g * a.kx;
-  const float* yp = a.Y + ob.y + on.y + (int64_t)g * a.ky;
+  int64_t kb = 0, ke = a.K;
+  if constexpr (SPLIT) {
+    const int64_t kq = (a.K + 7) / 8 * 2;  // a quarter of the sum, rounded up to an even count
+    kb = wv * kq < a.K ? wv * kq : a.K;
+    ke = kb + kq < a.K ? kb + kq : a.K;
+  }
+  const float* xp = a.X + ob.x + om.x + (kb + g) * a.kx;
+  const float* yp = a.Y + ob.y + on.y + (kb + g) * a.ky;
   const int64_t kx2 = 2 * a.kx, ky2 = 2 * a.ky;
   f16v acc = {};
-  int64_t k0 = 0;
-  for (; k0 + 16 <= a.K; k0 += 16) {  // eight steps with every load issued first
+  int64_t k0 = kb;
+  for (; k0 + 16 <= ke; k0 += 16) {  // eight steps with every load issued first
     float av[8], bv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -523,16 +534,29 @@ __global__ __launch_bounds__(256) void einsum_gemm_kernel(GemmArgs a) {
     xp += 8 * kx2;
     yp += 8 * ky2;
   }
-  for (; k0 < a.K; k0 += 2) {
-    const bool kv = k0 + g < a.K;
+  for (; k0 < ke; k0 += 2) {
+    const bool kv = k0 + g < ke;
     const float av = (mv && kv) ? xp[0] : 0.f;
     const float bv = (nv && kv) ? yp[0] : 0.f;
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     xp += kx2;
     yp += ky2;
   }
+  if constexpr (SPLIT) {
+    __shared__ float red[3][16][64];
+    if (wv > 0) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) red[wv - 1][v][lane] = acc[v];
+    }
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] += red[q][v][lane];
+  }
   // rows of this lane's accumulator registers: their output offsets come from
-  // the lanes that own those rows (every lane takes part in the shuffles)
+  // the lanes that own those rows (every lane of the wave takes part)
   const int64_t base = ob.o + on.o;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -625,9 +649,13 @@ int launch_einsum(const EinsumArgs& a_in, void* stream) {
   for (int d = 0; d < a.n_sum; ++d) n_sum *= a.sum_size[d];
   GemmArgs ga;
   if (gemm_args(a, ga) && ga.M >= 8 && ga.N >= 8 && ga.M * ga.N * ga.B * ga.K >= (int64_t(1) << 20)) {
-    const int64_t waves = ga.tiles_m * ga.tiles_n * ga.B;
-    if ((waves + 3) / 4 < (int64_t(1) << 31)) {
-      hipLaunchKernelGGL(einsum_gemm_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
+    const int64_t tiles = ga.tiles_m * ga.tiles_n * ga.B;
+    if (tiles < 2048 && ga.K >= 64) {  // too few tiles to fill the chip: four waves per tile
+      hipLaunchKernelGGL(einsum_gemm_kernel<true>, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, ga);
+      return (int)hipGetLastError();
+    }
+    if ((tiles + 3) / 4 < (int64_t(1) << 31)) {
+      hipLaunchKernelGGL(einsum_gemm_kernel<false>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0,
                          (hipStream_t)stream, ga);
       return (int)hipGetLastError();
     }
