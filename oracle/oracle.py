@@ -384,29 +384,36 @@ def fit(model_str, factors, Y, M, alpha, beta, eps=1e-10, n_sweeps=1,
 def kkt_residual(model_str, factors, Y, M, alpha, beta, eps):
     """Stationarity residual of the constrained problem (eq. 3.1).
 
-    dL/dtheta_u = (D_u - N_u)/alpha (from eq. 3.6 and the derivative of the
-    divergence).  Interior entries need N = D; entries at the floor eps need
-    (D - N)/alpha >= 0.  Returns max over interior |N/D - 1| plus the largest
-    violation at the floor, over all blocks.
+    With r = N/D, the update multiplies theta by g^{-1}(r) (eq. 3.4), whose
+    fixed point is r = g(1): 1 for the power updates, 0 for the exponential
+    ones (alpha = 0 with beta = 1, and Jensen-Shannon).  The gradient is
+    dL/dtheta_u = -s (N_u - g(1) D_u) with s of the sign of alpha for the
+    (alpha, beta) family (from eq. 3.6 and dL/dy = (b - a)/alpha) and s > 0
+    for the other families.  Interior entries need r = g(1); entries at the
+    floor eps need dL/dtheta >= 0, i.e. sign(s) (r - g(1)) <= 0.  Returns the
+    largest |r - g(1)| over interior entries plus the largest violation at the
+    floor, maximised over blocks.
     """
+    kind, _ = update_rule(alpha, beta)
+    g1 = 0.0 if kind == "exp" else 1.0
+    sgn = -1.0 if (not isinstance(alpha, Family) and alpha < 0) else 1.0
     worst = 0.0
     for ell in range(len(factors)):
         N, D = numerator_denominator(model_str, factors, ell, Y, M, alpha, beta)
         th = np.asarray(factors[ell])
         pos = D > 0
-        r = np.where(pos, N / np.where(pos, D, 1.0), 1.0)
+        r = np.where(pos, N / np.where(pos, D, 1.0), g1)
         interior = (th > eps * (1 + 1e-9)) & pos
         at_floor = (~interior) & pos
-        v_int = float(np.max(np.abs(r[interior] - 1.0), initial=0.0))
-        sgn = 1.0 if alpha > 0 else -1.0
-        v_floor = float(np.max(np.maximum(0.0, sgn * (r[at_floor] - 1.0)), initial=0.0))
+        v_int = float(np.max(np.abs(r[interior] - g1), initial=0.0))
+        v_floor = float(np.max(np.maximum(0.0, sgn * (r[at_floor] - g1)), initial=0.0))
         worst = max(worst, v_int + v_floor)
     return worst
 
 
 # --------------------------------------------------------------------------
 # Train / validation splits and the stopping rule (Sec. 6, "Experimental
-# design"; App. A, "Stopping criterion")
+# design"; App. B, "Algorithmic Details", stopping criterion)
 # --------------------------------------------------------------------------
 STOP_MAX, STOP_TRAIN_TOL, STOP_VALIDATION = 0, 1, 2
 

@@ -216,3 +216,48 @@ def test_eps_floor():
     assert out[0][0, 0] == 1e-10            # N = 0 < D: the floor (proof of Lemma 4.2)
     f = O.fit("ir,jr->ij", [np.full((2, 1), 1e-20), H], Y + 1, None, 1.0, 0.0, 1e-10, n_sweeps=0)
     assert np.all(f[0] == 1e-10)            # init clamped
+
+
+@pytest.mark.parametrize("ab,c,expected", [((1.0, 0.0), 2.0, 1.0), ((1.0, 0.0), 0.5, 0.0),
+                                           ((-1.0, 2.0), 2.0, 0.5), ((-1.0, 2.0), 0.5, 0.0)])
+def test_kkt_residual_floor_branch_by_hand(ab, c, expected):
+    """'ir,jr->ij' with I = 2, J = 2, R = 1: w1 sits at the floor, w2 = 1 and
+    h are interior; y_2j = yhat_2j and y_1j = c yhat_1j.  By hand: the interior
+    ratios of block H are 1 + O(eps); at the floor r_w1 = sum_j a_1j h_j /
+    sum_j b_1j h_j, which is c for KL (a = y/yhat, b = 1) and 1/c for
+    (alpha, beta) = (-1, 2) (a = yhat/y, b = 1).  KKT needs dL/dtheta >= 0 at
+    the floor: r <= 1 when alpha > 0, r >= 1 when alpha < 0; the residual is
+    the size of the violation."""
+    eps = 1e-10
+    W = np.array([[eps], [1.0]])
+    H = np.array([[1.0], [2.0]])
+    Yhat = W @ H.T
+    Y = Yhat.copy()
+    Y[0] *= c
+    got = O.kkt_residual("ir,jr->ij", [W, H], Y, None, *ab, eps)
+    assert abs(got - expected) <= 1e-8, got
+
+
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (0.0, 1.0), (O.jensen_shannon(), None),
+                                        (O.negbin(3.0), None)])
+def test_kkt_residual_zero_at_exact_fit(alpha, beta):
+    """At Y = Yhat every ratio sits at the update's fixed point g(1): 1 for the
+    power updates, 0 for the exponential ones (alpha = 0, beta = 1 and
+    Jensen-Shannon), so the residual is zero in every family."""
+    g = np.random.default_rng(7)
+    f = [g.gamma(1.0, 1.0, size=s) + 0.1 for s in ((5, 3), (4, 3), (6, 3))]
+    Y = O.reconstruct("ir,jr,kr->ijk", f)
+    assert O.kkt_residual("ir,jr,kr->ijk", f, Y, None, alpha, beta, 1e-10) < 1e-12
+
+
+def test_kkt_residual_floor_reached_by_mu():
+    """KL NMF on data with an all-zero row: MU drives that row of W to the floor
+    (N = 0 there), which satisfies KKT; the residual still falls toward zero."""
+    g = np.random.default_rng(8)
+    W0, H0 = g.gamma(1.0, 1.0, size=(6, 2)), g.gamma(1.0, 1.0, size=(5, 2))
+    Y = W0 @ H0.T
+    Y[2] = 0.0
+    f = [g.gamma(1.0, 1.0, size=(6, 2)), g.gamma(1.0, 1.0, size=(5, 2))]
+    f = O.fit("ir,jr->ij", f, Y, None, 1.0, 0.0, 1e-10, n_sweeps=2000)
+    assert np.all(f[0][2] == 1e-10)
+    assert O.kkt_residual("ir,jr->ij", f, Y, None, 1.0, 0.0, 1e-10) < 1e-4
