@@ -321,7 +321,7 @@ nnef_status nnef_batch_autotune(nnef_batch_t batch, const float* const* Y, const
 size_t nnef_batch_describe(nnef_batch_t batch, char* buf, size_t buf_len);
 
 /* ------------------------------------------------------------------------
- * Splits and early stopping (Sec. 6, "Experimental design"; App. A,
+ * Splits and early stopping (Sec. 6, "Experimental design"; App. B,
  * "Stopping criterion").  A split mask holds one byte per entry: entries
  * equal to train_value (default 1) are fitted, val_value (default 2) marks
  * the validation set, any other value (0 missing, 3 heldout, ...) is unused.

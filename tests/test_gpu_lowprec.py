@@ -55,7 +55,7 @@ def test_bf16_loss_trace_stays_fp32_accurate():
 
 def test_bf16_trajectory_final_loss():
     """50 sweeps with BF16 contractions reach the FP64 oracle's 50-sweep loss
-    within 1e-3 relative (both losses evaluated by the oracle)."""
+    within 1e-4 relative (both losses evaluated by the oracle)."""
     p = CASES["cp3_small_kl"]()
     plan = _plan(p, "bf16")
     g = gpu_sweeps(plan, p, clamp_init(p), 50)
@@ -63,4 +63,4 @@ def test_bf16_trajectory_final_loss():
     lg = O.loss(p.model_str, [x.astype(np.float64) for x in g], p.Y, p.M, p.alpha, p.beta)
     lr = O.loss(p.model_str, ref, p.Y, p.M, p.alpha, p.beta)
     print(f"bf16 50-sweep loss {lg:.8e} oracle {lr:.8e} rel {(lg - lr) / lr:.2e}")
-    assert abs(lg - lr) <= 1e-3 * lr
+    assert abs(lg - lr) <= 1e-4 * lr
