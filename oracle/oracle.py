@@ -121,14 +121,31 @@ def einsum(expr: str, *operands):
                      optimize=True)
 
 
-def brute_einsum(expr: str, *operands):
+def einsum_to(expr: str, out_shape, *operands):
+    """einsum whose output may hold letters that no input holds.
+
+    A latent letter that appears in one operand only is summed inside it
+    (Sec. 2); in the numerator einsum of that operand (eq. 3.6) the letter is
+    then an output letter of no input, and the contraction is the same for
+    every value of it.  ``out_shape`` gives its size.
+    """
+    lhs, out = expr.replace(" ", "").split("->")
+    present = set(lhs.replace(",", ""))
+    kept = "".join(c for c in out if c in present)
+    r = einsum(lhs + "->" + kept, *operands)
+    idx = tuple(slice(None) if c in present else None for c in out)
+    return np.array(np.broadcast_to(r[idx], tuple(out_shape)))
+
+
+def brute_einsum(expr: str, *operands, sizes=None):
     """Nested loops over every letter combination (definition of einsum).
 
-    Used only on tiny inputs to pin ``einsum``.
+    Used only on tiny inputs to pin ``einsum``.  ``sizes`` gives the size of
+    output letters that no operand holds.
     """
     lhs, out = expr.replace(" ", "").split("->")
     ops = lhs.split(",")
-    size = {}
+    size = dict(sizes or {})
     for t, o in zip(ops, operands):
         for ch, n in zip(t, np.shape(o)):
             size[ch] = n
@@ -329,7 +346,8 @@ def numerator_denominator(model_str, factors, ell, Y, M, alpha, beta):
     opsA[ell] = A
     opsB = list(factors)
     opsB[ell] = B
-    return einsum(es, *opsA), einsum(es, *opsB)
+    shape = np.shape(factors[ell])
+    return einsum_to(es, shape, *opsA), einsum_to(es, shape, *opsB)
 
 
 def apply_update(theta, N, D, alpha, beta, eps):

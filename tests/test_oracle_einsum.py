@@ -22,7 +22,8 @@ FAMILIES = [
     ("i,jr,kr->ijk", dict(i=3, j=2, k=2, r=2)),                        # custom (Sec. 2)
     ("ir,js,ks,rs->ijk", dict(i=2, j=2, k=3, r=2, s=3)),               # custom (Sec. 2)
     ("wr,dr,hr,irk,jrk->wdhij", dict(w=2, d=2, h=2, i=2, j=2, r=2, k=2)),  # Uber model (Sec. 6)
-    ("ir,jr,ak,kr,tr->ijat", dict(i=2, j=2, a=3, t=2, r=2, k=2)),      # ICEWS model (Sec. 6)
+    ("ir,jr,ak,kr,tr->ijat", dict(i=2, j=2, a=3, t=2, r=2, k=2)),      # ICEWS model (Sec. 2, 6)
+    ("rij,jk,ik->ijk", dict(i=3, j=2, k=2, r=3)),                      # latent letter in one operand
 ]
 
 
@@ -70,8 +71,8 @@ def test_numerator_is_gradient_contraction(model_str, sizes):
         es = O.swap(model_str, ell)
         ops = list(f)
         ops[ell] = A
-        N = O.einsum(es, *ops)
-        np.testing.assert_allclose(N, O.brute_einsum(es, *ops), rtol=1e-13, atol=1e-15)
+        N = O.einsum_to(es, f[ell].shape, *ops)
+        np.testing.assert_allclose(N, O.brute_einsum(es, *ops, sizes=sizes), rtol=1e-13, atol=1e-15)
         jac = np.zeros(f[ell].shape)
         for u in np.ndindex(f[ell].shape):
             e = np.zeros(f[ell].shape)
