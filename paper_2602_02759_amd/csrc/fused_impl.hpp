@@ -97,22 +97,62 @@ __device__ __forceinline__ void ab_weights(float y, float yh, float al, float be
   }
 }
 
-// (1+u) log(1+u) - u, accurate near u = 0 (series below |u| < 1/4).
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLog2e = 1.44269504088896341f;
+
+// log(1 + u) for u > -1, accurate near u = 0: below |u| < 1/4 through
+// 2 atanh(s), s = u / (2 + u), by its odd series (|s| < 1/7, error < 1e-9
+// relative); elsewhere 1 + u is far from 1 and the hardware logarithm is
+// accurate relative to its result.
+__device__ __forceinline__ float log1p_acc(float u) {
+  if (fabsf(u) < 0.25f) {
+    const float s = u * fast_rcp(2.f + u), s2 = s * s;
+    return 2.f * s * (1.f + s2 * (1.f / 3 + s2 * (1.f / 5 + s2 * (1.f / 7 + s2 * (1.f / 9)))));
+  }
+  return fast_log2(1.f + u) * kLn2;
+}
+
+// e^z - 1 - z, accurate near z = 0 (Taylor series through z^10 below |z| < 1/2).
+__device__ __forceinline__ float expm1_m(float z) {
+  if (fabsf(z) < 0.5f) {
+    float s = 1.f / 3628800;
+    const float inv[8] = {1.f / 362880, 1.f / 40320, 1.f / 5040, 1.f / 720, 1.f / 120, 1.f / 24, 1.f / 6,
+                          1.f / 2};
+#pragma unroll
+    for (int n = 0; n < 8; ++n) s = s * z + inv[n];
+    return s * z * z;
+  }
+  return fast_exp2(z * kLog2e) - 1.f - z;
+}
+
+// 1 - e^z + z e^z = sum_{m >= 2} (m - 1) z^m / m!, accurate near z = 0.
+__device__ __forceinline__ float xexp_m(float z) {
+  if (fabsf(z) < 0.5f) {
+    // coefficients (m - 1)/m! for m = 10 .. 3, then 1/2 for m = 2
+    const float c[8] = {9.f / 3628800, 8.f / 362880, 7.f / 40320, 6.f / 5040, 5.f / 720, 4.f / 120,
+                        3.f / 24, 2.f / 6};
+    float s = c[0];
+#pragma unroll
+    for (int n = 1; n < 8; ++n) s = s * z + c[n];
+    return (s * z + 0.5f) * z * z;
+  }
+  return 1.f + (z - 1.f) * fast_exp2(z * kLog2e);
+}
+
+// (1+u) log(1+u) - u for u >= -1, accurate near u = 0 (series below |u| < 1/4).
 __device__ __forceinline__ float xlogx_m(float u) {
   if (fabsf(u) < 0.25f) {
-    // sum_{n>=2} (-1)^n u^n / (n (n-1))
+    // sum_{n>=2} (-1)^n u^n / (n (n-1)), through n = 12
     float s = 0.f, un = u * u;
-    const float inv[9] = {1.f / 2, 1.f / 6, 1.f / 12, 1.f / 20, 1.f / 30, 1.f / 42, 1.f / 56,
-                          1.f / 72, 1.f / 90};
 #pragma unroll
-    for (int n = 0; n < 9; ++n) {
-      s += ((n & 1) ? -inv[n] : inv[n]) * un;
+    for (int n = 2; n <= 12; ++n) {
+      s += ((n & 1) ? -1.f : 1.f) / (float)(n * (n - 1)) * un;
       un *= u;
     }
     return s;
   }
-  float t = 1.f + u;
-  return t * (fast_log2(t) * 0.69314718055994531f) - u;
+  const float t = 1.f + u;
+  return (t > 0.f ? t * (fast_log2(t) * kLn2) : 0.f) - u;
 }
 
 // u - log(1+u), accurate near u = 0.
@@ -120,55 +160,74 @@ __device__ __forceinline__ float u_mlog(float u) {
   if (fabsf(u) < 0.25f) {
     float s = 0.f, un = u * u;
 #pragma unroll
-    for (int n = 2; n < 11; ++n) {
-      s += ((n & 1) ? -1.f : 1.f) * un / (float)n;
+    for (int n = 2; n <= 12; ++n) {
+      s += ((n & 1) ? -1.f : 1.f) / (float)n * un;
       un *= u;
     }
     return s;
   }
-  return u - fast_log2(1.f + u) * 0.69314718055994531f;
+  return u - fast_log2(1.f + u) * kLn2;
 }
 
 // D_{alpha,beta}(y, yh) of App. B for one observed entry, as float.  The
 // specialised weight kinds fix the case; WK_GEN selects it at run time.
+// Near a fit (y close to yh) every case is written so that no two large
+// terms cancel: the relative residual u = (y - yh)/yh is formed from the
+// difference y - yh (exact when y and yh are within a factor of two), and
+// the cases that are differences of powers are rewritten through
+// t = log(y/yh) with series for e^z - 1 - z and 1 - e^z + z e^z:
+//   generic:     yh^(a+b)/(a b) [a/(a+b) E((a+b) t) - E(a t)],  E(z) = e^z - 1 - z
+//   beta = 0:    yh^a/a^2 F(a t),  F(z) = 1 - e^z + z e^z
+//   alpha = -b:  E(a t)/a^2
+// (algebraically identical to the definitions; used while |t| <= 1, where no
+// overflow can occur, the definitions as written beyond).
 template <int WK>
 __device__ __forceinline__ float ab_loss(float y, float yh, const FusedArgs& a) {
-  const float ln2 = 0.69314718055994531f;
-  if constexpr (WK == WK_KL) {  // y log(y/yh) - y + yh = yh [(1+u) log(1+u) - u], u = y/yh - 1
-    return y > 0.f ? yh * xlogx_m(y / yh - 1.f) : yh;
+  if constexpr (WK == WK_KL) {  // y log(y/yh) - y + yh = yh [(1+u) log(1+u) - u]
+    return y > 0.f ? yh * xlogx_m((y - yh) * fast_rcp(yh)) : yh;
   } else if constexpr (WK == WK_EUC) {
     const float d = y - yh;
     return 0.5f * d * d;
   } else if constexpr (WK == WK_IS) {  // y/yh - log(y/yh) - 1 = u - log(1+u)
-    return u_mlog(y / yh - 1.f);
+    return u_mlog((y - yh) * fast_rcp(yh));
   } else if constexpr (WK == WK_SQRT) {  // (1/2, 1): (2/3)(sqrt y - sqrt yh)^2 (sqrt y + 2 sqrt yh)
     const float sy = __builtin_sqrtf(y), v = __builtin_sqrtf(yh), d = sy - v;
     return (2.f / 3.f) * d * d * (sy + 2.f * v);
   } else if constexpr (WK == WK_RKL) {  // (0, 1): yh log(yh/y) - yh + y
-    return y > 0.f ? y * xlogx_m(yh / y - 1.f) : INFINITY;
+    return y > 0.f ? y * xlogx_m((yh - y) * fast_rcp(y)) : INFINITY;
   } else if constexpr (WK == WK_FAM) {
     const float ph = a.fparam;
     if (a.lk == LK_NB)  // (phi + y) log(phi + yh) - y log yh
-      return ((ph + y) * fast_log2(ph + yh) - (y > 0.f ? y * fast_log2(yh) : 0.f)) * ln2;
+      return ((ph + y) * fast_log2(ph + yh) - (y > 0.f ? y * fast_log2(yh) : 0.f)) * kLn2;
     if (a.lk == LK_BIN)  // n log(1 + yh) - y log yh
-      return ph * log1pf(yh) - (y > 0.f ? y * fast_log2(yh) * ln2 : 0.f);
-    // Jensen-Shannon: (y log y + yh log yh)/2 - m log m, m = (y + yh)/2, written as
-    // (y log(y/m) + yh log(yh/m))/2
-    const float m = 0.5f * (y + yh);
-    const float ty = y > 0.f ? y * fast_log2(y / m) : 0.f;
-    return 0.5f * (ty + yh * fast_log2(yh / m)) * ln2;
+      return ph * log1pf(yh) - (y > 0.f ? y * fast_log2(yh) * kLn2 : 0.f);
+    // Jensen-Shannon: (y log(y/m) + yh log(yh/m))/2, m = (y + yh)/2.  With
+    // y = m (1 + v), yh = m (1 - v): (m/2) [h(v) + h(-v)], h(u) = (1+u) log(1+u) - u >= 0
+    const float s = y + yh, v = (y - yh) * fast_rcp(s);
+    return 0.25f * s * (xlogx_m(v) + xlogx_m(-v));
   } else {
     const float al = a.alpha, be = a.beta;
-    if (a.lk == LK_GENERIC)
+    float t = 0.f;
+    bool near = false;
+    if (y > 0.f) {
+      t = log1p_acc((y - yh) * fast_rcp(yh));
+      near = fabsf(t) <= 1.f;
+    }
+    if (a.lk == LK_GENERIC) {
+      if (near)
+        return a.ab_inv * powpos(yh, al + be) * (al * a.apb_inv * expm1_m((al + be) * t) - expm1_m(al * t));
       return a.ab_inv * (al * a.apb_inv * powpos(y, al + be) + be * a.apb_inv * powpos(yh, al + be) -
                          powpos(y, al) * powpos(yh, be));
+    }
     if (a.lk == LK_BETA0) {
+      if (near) return powpos(yh, al) * xexp_m(al * t) / (al * al);
       const float ya = powpos(y, al);
-      const float lg = y > 0.f ? ya * fast_log2(y / yh) * ln2 : 0.f;
+      const float lg = y > 0.f ? ya * fast_log2(y / yh) * kLn2 : 0.f;
       return (powpos(yh, al) - ya + al * lg) / (al * al);
     }
     // alpha = -beta
-    return (powpos(y, al) / powpos(yh, al) - 1.f + al * fast_log2(yh / y) * ln2) / (al * al);
+    if (near) return expm1_m(al * t) / (al * al);
+    return (powpos(y, al) / powpos(yh, al) - 1.f + al * fast_log2(yh / y) * kLn2) / (al * al);
   }
 }
 

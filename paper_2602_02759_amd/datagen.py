@@ -132,6 +132,17 @@ def gamma_noise_problem(name, model_str, sizes, alpha, beta, *, seed,
                    init_factors(model_str, sizes, seed), truth, n_sweeps)
 
 
+def exact_problem(name, model_str, sizes, alpha, beta, *, seed, truth_shape=1.0,
+                  missing=0.0, n_sweeps=1):
+    """Y = einsum(model_str, truth) exactly (no noise), truth ~ Gamma(shape, 1):
+    data of exact rank, so a fit of that rank drives the residuals to zero."""
+    truth = gamma_factors(model_str, sizes, truth_shape, 1.0, rng(seed, STREAM_TRUTH))
+    Y = np.ascontiguousarray(mean_tensor(model_str, truth), dtype=np.float32)
+    M = bernoulli_mask(Y.shape, missing, seed)
+    return Problem(name, model_str, dict(sizes), alpha, beta, Y, M,
+                   init_factors(model_str, sizes, seed), truth, n_sweeps)
+
+
 def negbin_problem(name, model_str, sizes, phi, *, seed, truth_shape, missing=0.0):
     """Y ~ NegBinom(mean einsum(model_str, truth), dispersion phi)."""
     truth = gamma_factors(model_str, sizes, truth_shape, 1.0, rng(seed, STREAM_TRUTH))
