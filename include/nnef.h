@@ -61,10 +61,11 @@ typedef enum {
 
 /* Input precision of the numerator and denominator contractions (the einsums
  * with a(Y,Yhat) and b(Y,Yhat) of Algorithm 1) on MFMA, with FP32
- * accumulation.  It applies to blocks whose contraction width is 17..32; other
- * widths, the reconstruction Yhat, the weights, the ratio N/D, the power and
- * the update, and the loss terms are float32; loss sums are float64.
- * nnef_plan_describe reports the precision chosen for every block. */
+ * accumulation.  It applies to every block of the bilinear lowering (widths
+ * up to 64; in batched plans to width 32 only); blocks on the direct lowering
+ * (see nnef_plan), the reconstruction Yhat, the weights, the ratio N/D, the
+ * power and the update, and the loss terms are float32; loss sums are
+ * float64.  nnef_plan_describe reports the precision chosen for every block. */
 typedef enum { NNEF_FP32 = 0, NNEF_BF16 = 1, NNEF_FP16 = 2 } nnef_prec;
 
 /* Likelihood family.  NNEF_AB: the (alpha, beta)-divergence (App. B), with
@@ -95,6 +96,18 @@ void nnef_default_options(nnef_options* opt);
 
 /*
  * nnef_plan - parse and lower a model string; allocate the plan's workspace.
+ * Every block update is lowered one of two ways; neither stores the
+ * reconstruction (one value per data entry) in device memory:
+ *   bilinear  the observed modes split into rows P (holding operand l's
+ *             modes) and columns Q with Yhat[p,q] = sum_k L[p,k] R[q,k] over a
+ *             contraction width of at most 64, computed tile by tile on MFMA;
+ *   direct    when no such split exists (the many-body models of Sec. 2, such
+ *             as "ij,jk,ik->ijk", or CP-like ranks above 64): each data
+ *             entry's reconstruction is summed over its latent combinations in
+ *             registers (FP32 vector arithmetic).  Limits: at most 8 operands,
+ *             at most 256 latent combinations in operand l, and at most 6144
+ *             (other operands x all latent combinations).
+ * nnef_plan_describe names the lowering of every block.
  *   model_str : e.g. "ir,jr,kr->ijk" or "ia,jab,kbc,lc->ijkl" (eq. 2.2).
  *   mode_sizes: n_modes sizes, in the order of the output letters.
  *   ranks     : n_ranks sizes of the contracted letters, in order of their
@@ -110,8 +123,9 @@ void nnef_default_options(nnef_options* opt);
  *                 2^30 or more data entries;
  *   NNEF_E_LOSS_UNSUPPORTED  alpha = 0 with beta != 1 (App. B gives no
  *                 decomposition), non-finite alpha or beta;
- *   NNEF_E_UNSUPPORTED  a block whose contraction width exceeds 64 in every
- *                 lowering the planner knows.
+ *   NNEF_E_UNSUPPORTED  a block with no bilinear split of width <= 64 that
+ *                 is also beyond the limits of the direct lowering (the
+ *                 message names the block and the limit).
  * Synchronises the device once (workspace set-up).
  */
 nnef_status nnef_plan(const char* model_str, const int64_t* mode_sizes, int n_modes,

@@ -18,8 +18,10 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnnef.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "learned.hip", "fused16.hip", "fused32.hip", "fused64.hip",
-           "fused16b.hip", "fused32b.hip", "fused64b.hip", "planner.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "learned.hip", "fused16.hip", "fused32.hip", "fused64.hip", "fused16bf.hip",
+           "fused16h.hip", "fused64bf.hip", "fused64h.hip",
+           "fused16b.hip", "fused32b.hip", "fused64b.hip", "direct.hip", "planner.cpp",
+           "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel
@@ -49,7 +51,7 @@ def _compile(src: str, defines=(), tag="", incremental=False) -> str:
 
 
 def build(verbose: bool = False, out: str = LIB, defines=(), incremental: bool = False) -> str:
-    """Compile and link; ``defines`` (e.g. ``["NNEF_PT32=4"]``) select tile variants.
+    """Compile and link; ``defines`` are passed to every compile as -D options.
     ``incremental`` reuses objects newer than their source and every header."""
     os.makedirs(BUILD, exist_ok=True)
     tag = "".join("." + d.replace("=", "_") for d in defines)

@@ -198,11 +198,16 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
   for (int l = 0; l < (int)m.ops.size(); ++l) {
     BlockPlan bp;
     Status st = lower_block(m, l, bp, p->ws_sizes, err, direct_only);
+    if (st == ST_UNSUPPORTED && !direct_only) {  // no bilinear split: per-entry latent sums
+      std::string err2;
+      st = lower_direct(m, l, bp, p->ws_sizes, err2, target_wg);
+      if (st != ST_OK) err += "; " + err2;
+    }
     if (st != ST_OK) {
       free_plan(p);
       return fail(st == ST_UNSUPPORTED ? NNEF_E_UNSUPPORTED : NNEF_E_SHAPE, err);
     }
-    if (!choose_geometry(m, bp, target_wg)) {
+    if (!bp.direct && !choose_geometry(m, bp, target_wg)) {
       free_plan(p);
       return fail(NNEF_E_SHAPE, "grid too large");
     }
@@ -227,7 +232,8 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
   }
   if (dry_run) {  // lowering and geometry only: no device memory
     for (const auto& bp : p->blocks) {
-      const bool lp = bp.KP == 32 && bp.qstep == 32 && p->opt.prec != NNEF_FP32;
+      // batched plans (direct_only) contract in FP32 at widths 16 and 64
+      const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!direct_only || bp.KP == 32);
       p->description += describe_block(m, bp) +
                         (lp ? (p->opt.prec == NNEF_BF16 ? " contract=bf16" : " contract=fp16") : " contract=fp32") +
                         "\n";
@@ -271,6 +277,27 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
     }
   }
   for (auto& bp : p->blocks) {
+    if (bp.direct) {
+      nnef_status st = upload_table(p, offsets_table(m, bp.P), &bp.d_poff);
+      if (st == NNEF_OK) st = upload_table(p, offsets_table(m, bp.Q), &bp.d_yq);
+      if (st == NNEF_OK) st = upload_table(p, offsets_in(m, bp.P, m.ops[bp.ell]), &bp.d_thp);
+      if (st == NNEF_OK) st = upload_table(p, offsets_in(m, bp.kappa, m.ops[bp.ell]), &bp.d_thr);
+      for (int o : bp.others) {
+        uint32_t *tp = nullptr, *tq = nullptr, *tl = nullptr;
+        if (st == NNEF_OK) st = upload_table(p, offsets_in(m, bp.P, m.ops[o]), &tp);
+        if (st == NNEF_OK) st = upload_table(p, offsets_in(m, bp.Q, m.ops[o]), &tq);
+        if (st == NNEF_OK) st = upload_table(p, offsets_in(m, bp.kappa + bp.S, m.ops[o]), &tl);
+        bp.d_opp.push_back(tp);
+        bp.d_opq.push_back(tq);
+        bp.d_oplat.push_back(tl);
+      }
+      if (st != NNEF_OK) {
+        free_plan(p);
+        return st;
+      }
+      p->description += describe_block(m, bp) + " contract=fp32\n";
+      continue;
+    }
     nnef_status st = upload_table(p, offsets_table(m, bp.P), &bp.d_poff);
     if (st == NNEF_OK) st = upload_table(p, offsets_table(m, bp.qo), &bp.d_qoyoff);
     if (st == NNEF_OK) {
@@ -288,7 +315,8 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
       free_plan(p);
       return st;
     }
-    const bool lp = bp.KP == 32 && bp.qstep == 32 && p->opt.prec != NNEF_FP32;
+    // batched plans (direct_only) contract in FP32 at widths 16 and 64
+      const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!direct_only || bp.KP == 32);
     p->description += describe_block(m, bp) +
                       (lp ? (p->opt.prec == NNEF_BF16 ? " contract=bf16" : " contract=fp16") : " contract=fp32") + "\n";
   }
@@ -416,9 +444,49 @@ static FusedArgs fused_args(const nnef_plan_s* p, const BlockPlan& bp, const flo
   a.apb_inv = apb != 0 ? (float)(1.0 / apb) : 0.f;
   a.lk = p->ls.lk;
   a.fparam = (float)p->ls.fparam;
-  a.prec = (bp.KP == 32 && bp.qstep == 32) ? p->opt.prec : 0;
+  a.prec = p->opt.prec;
   a.full = (bp.K == bp.KP && bp.nqi % bp.qstep == 0 && bp.nP % bp.rows == 0 && bp.in_stride == 1 &&
             bp.pieces[bp.inner].ld == bp.KP) ? 1 : 0;
+  return a;
+}
+
+static DirectArgs direct_args(const nnef_plan_s* p, const BlockPlan& bp, const float* Y, bool masked,
+                              const float* const* factors) {
+  DirectArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.Y = Y;
+  a.masked = masked ? 1 : 0;
+  a.nP = (int)bp.nP;
+  a.nQ = (int)bp.nQ;
+  a.yp = bp.d_poff;
+  a.yq = bp.d_yq;
+  a.theta = factors[bp.ell];
+  a.thp = bp.d_thp;
+  a.thr = bp.d_thr;
+  a.K = bp.K;
+  a.KS = bp.KS;
+  a.G = bp.G;
+  a.n_ops = (int)bp.others.size();
+  for (int j = 0; j < a.n_ops; ++j) {
+    a.op[j] = factors[bp.others[j]];
+    a.opp[j] = bp.d_opp[j];
+    a.opq[j] = bp.d_opq[j];
+    a.oplat[j] = bp.d_oplat[j];
+  }
+  a.rows_per_wg = bp.rows_per_wg;
+  a.qlanes = bp.qlanes;
+  a.q_per_chunk = bp.q_per_chunk;
+  a.n_chunks = bp.n_chunks;
+  a.n_panels = bp.n_panels;
+  a.partN = p->partN;
+  a.partD = p->partD;
+  a.alpha = (float)p->ls.alpha;
+  a.beta = (float)p->ls.beta;
+  const double ab = p->ls.alpha * p->ls.beta, apb = p->ls.alpha + p->ls.beta;
+  a.ab_inv = ab != 0 ? (float)(1.0 / ab) : 0.f;
+  a.apb_inv = apb != 0 ? (float)(1.0 / apb) : 0.f;
+  a.lk = p->ls.lk;
+  a.fparam = (float)p->ls.fparam;
   return a;
 }
 
@@ -437,18 +505,29 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
   const float* const* cf = factors;
   for (int l = 0; l < L; ++l) {
     const BlockPlan& bp = p->blocks[l];
-    int e = run_side_prep(p, bp, cf, s);
-    if (e) return hip_fail(e, "side-operand contraction launch");
-    FusedArgs fa = fused_args(p, bp, Yd, masked, cf);
     const bool want_loss = loss_slot && l == 0;
-    fa.loss_part = want_loss ? p->loss_part : nullptr;
+    int e = 0;
+    FusedArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    if (!bp.direct) {
+      e = run_side_prep(p, bp, cf, s);
+      if (e) return hip_fail(e, "side-operand contraction launch");
+      fa = fused_args(p, bp, Yd, masked, cf);
+      fa.loss_part = want_loss ? p->loss_part : nullptr;
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (p->timing) {
       if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess ||
           hipEventRecord(ev0, s) != hipSuccess)
         return fail(NNEF_E_DEVICE, "timing event set-up failed");
     }
-    e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, want_loss ? 1 : 0, s);
+    if (bp.direct) {
+      DirectArgs da = direct_args(p, bp, Yd, masked, cf);
+      da.loss_part = want_loss ? p->loss_part : nullptr;
+      e = launch_direct(da, p->ls.wk, want_loss ? 1 : 0, s);
+    } else {
+      e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, want_loss ? 1 : 0, s);
+    }
     if (e) return hip_fail(e, "fused pass launch");
     if (p->timing) {
       if (hipEventRecord(ev1, s) != hipSuccess) return fail(NNEF_E_DEVICE, "timing event record failed");
@@ -506,11 +585,18 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
 static nnef_status run_loss(nnef_plan_s* p, const float* Yd, bool masked, const float* const* factors,
                             double* d_loss, hipStream_t s) {
   const BlockPlan& bp = p->blocks[0];
-  int e = run_side_prep(p, bp, factors, s);
-  if (e) return hip_fail(e, "side-operand contraction launch");
-  FusedArgs fa = fused_args(p, bp, Yd, masked, factors);
-  fa.loss_part = p->loss_part;
-  e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, 2, s);
+  int e = 0;
+  if (bp.direct) {
+    DirectArgs da = direct_args(p, bp, Yd, masked, factors);
+    da.loss_part = p->loss_part;
+    e = launch_direct(da, p->ls.wk, 2, s);
+  } else {
+    e = run_side_prep(p, bp, factors, s);
+    if (e) return hip_fail(e, "side-operand contraction launch");
+    FusedArgs fa = fused_args(p, bp, Yd, masked, factors);
+    fa.loss_part = p->loss_part;
+    e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, 2, s);
+  }
   if (e) return hip_fail(e, "loss pass launch");
   e = launch_loss_final(p->loss_part, bp.n_wg, d_loss, s);
   if (e) return hip_fail(e, "loss reduction launch");
@@ -1079,6 +1165,7 @@ static nnef_status batch_tables(nnef_batch_s* b, const float* const* Y, const ui
             const int run = run0 + r;
             float* const* fr = factors + b->run_fac[run];
             FusedArgs a = fused_args(q, bp, Yd, msk, fr);
+            if (bp.KP != 32) a.prec = 0;  // batched passes of widths 16 and 64 contract in FP32
             a.partN = b->partN[run];
             a.partD = b->partD[run];
             a.loss_part = mode ? b->lpart[run] : nullptr;

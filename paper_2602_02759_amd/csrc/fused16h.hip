@@ -1,0 +1,8 @@
+// Fused-pass instantiations for contraction width 16 with FP16 contraction inputs.
+#include "fused_impl.hpp"
+
+namespace nnef {
+int launch_fused_kp16_fp16(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
+  return launch_fused_w<16, 2>(a, wk, vecq, mode, s);
+}
+}  // namespace nnef

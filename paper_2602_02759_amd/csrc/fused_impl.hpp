@@ -37,6 +37,33 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
+// 16x16x16 MFMA with BF16 (PREC 1) or FP16 (PREC 2) inputs rounded from FP32
+// and FP32 accumulation: lane (g, c) supplies A[row c][k 4g + j] = av[j] and
+// B[k 4g + j][col c] = bv[j], j = 0..3.
+template <int PREC>
+__device__ __forceinline__ f4 mfma4_lp(const float (&av)[4], const f4& bv, f4 c) {
+  if constexpr (PREC == 1) {
+    s4v x, y;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x[j] = __builtin_bit_cast(short, (__bf16)av[j]);
+      y[j] = __builtin_bit_cast(short, (__bf16)bv[j]);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, c, 0, 0, 0);
+  } else {
+    h4v x, y;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x[j] = (_Float16)av[j];
+      y[j] = (_Float16)bv[j];
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(x, y, c, 0, 0, 0);
+  }
+}
+
 // Loads at a 32-bit element offset from a wave-uniform base pointer.  The
 // offset is turned into a 32-bit byte offset so that the compiler can address
 // through the scalar base (no 64-bit address arithmetic per lane); every
@@ -237,12 +264,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-#ifndef NNEF_PT32
-#define NNEF_PT32 2
-#endif
 template <int KP>
 struct Tile {
-  static constexpr int PT = KP == 16 ? 4 : (KP == 32 ? NNEF_PT32 : 1);  // 16-wide p subtiles per wave
+  static constexpr int PT = KP == 16 ? 4 : (KP == 32 ? 2 : 1);  // 16-wide p subtiles per wave
   static constexpr int ROWS = 16 * PT;                          // rows of a panel
   static constexpr int KS = KP / 4;                             // reconstruction K steps
   static constexpr int KT = KP / 16;                            // kappa tiles of N and D
@@ -303,7 +327,10 @@ __device__ __forceinline__ void store_partial(const f4 (&acc)[Tile<KP>::PT][Tile
 
 // One workgroup's tile: braw is the workgroup index within the problem's
 // grid (before the XCD remap), slot its loss-partial index.
-template <int KP, int WK, bool VECQ, int MODE, bool FULL>
+// PREC: input precision of the numerator/denominator contractions (0 = FP32
+// on 16x16x4 f32 MFMA; 1 = BF16, 2 = FP16 on one 16x16x16 MFMA per kappa tile,
+// FP32 accumulation); the reconstruction is always FP32.
+template <int KP, int WK, bool VECQ, int MODE, bool FULL, int PREC>
 __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, int slot) {
   using T = Tile<KP>;
   constexpr int PT = T::PT, ROWS = T::ROWS, KS = T::KS, KT = T::KT, RST = T::RST;
@@ -532,15 +559,26 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
   auto contract = [&](int t, const Cols& cl, const f4& wa, const f4& wb) {
     if constexpr (ND) {
       // X^T[k][p] += sum_q C^T[k][q] W^T[q][p]   (scaled by u at flush)
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tN[t][kt] = mfma4(cl.Rb[kt][r], wa[r], tN[t][kt]);
-      if (!a.no_d) {
+      if constexpr (PREC == 0) {
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) tD[t][kt] = mfma4(cl.Rb[kt][r], wb[r], tD[t][kt]);
+          for (int r = 0; r < 4; ++r) tN[t][kt] = mfma4(cl.Rb[kt][r], wa[r], tN[t][kt]);
+        if (!a.no_d) {
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tD[t][kt] = mfma4(cl.Rb[kt][r], wb[r], tD[t][kt]);
+        }
+      } else {
+        // the K = 16 form sums the step's 16 columns q = 4g + r in one
+        // instruction: lane (g, c) supplies exactly its four r values
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) tN[t][kt] = mfma4_lp<PREC>(cl.Rb[kt], wa, tN[t][kt]);
+        if (!a.no_d) {
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt) tD[t][kt] = mfma4_lp<PREC>(cl.Rb[kt], wb, tD[t][kt]);
+        }
       }
     }
   };
@@ -559,7 +597,7 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
     __builtin_amdgcn_sched_group_barrier(0x008, KS, 0);
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
-      const int nm = (t + 1 < PT ? KS : 0) + (ND ? 8 * KT : 0);
+      const int nm = (t + 1 < PT ? KS : 0) + (ND ? (PREC == 0 ? 8 : 2) * KT : 0);
 #pragma unroll
       for (int j = 0; j < nm; ++j) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -649,57 +687,62 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
   }
 }
 
-template <int KP, int WK, bool VECQ, int MODE, bool FULL>
+template <int KP, int WK, bool VECQ, int MODE, bool FULL, int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_pass(FusedArgs a) {
-  fused_pass_body<KP, WK, VECQ, MODE, FULL>(a, blockIdx.x, blockIdx.x);
+  fused_pass_body<KP, WK, VECQ, MODE, FULL, PREC>(a, blockIdx.x, blockIdx.x);
 }
 
 // Persistent form over many problems (see fused_x32_batched).
-template <int KP, int WK, bool VECQ, int MODE, bool FULL>
+template <int KP, int WK, bool VECQ, int MODE, bool FULL, int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_pass_batched(
     const FusedArgs* __restrict__ args, const WorkItem* __restrict__ work, int n_work) {
   for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
     const WorkItem it = work[w];
     const FusedArgs a = args[it.run];
-    fused_pass_body<KP, WK, VECQ, MODE, FULL>(a, it.blk, it.blk);
+    fused_pass_body<KP, WK, VECQ, MODE, FULL, PREC>(a, it.blk, it.blk);
     __syncthreads();
   }
 }
 
 #ifndef NNEF_BATCHED_TU
-template <int KP, int WK, bool VECQ, int MODE>
+template <int KP, int WK, bool VECQ, int MODE, int PREC>
 int launch_fused_t(const FusedArgs& a, hipStream_t s) {
   if (a.full)
-    hipLaunchKernelGGL((fused_pass<KP, WK, VECQ, MODE, true>), dim3(a.n_wg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((fused_pass<KP, WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((fused_pass<KP, WK, VECQ, MODE, false>), dim3(a.n_wg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((fused_pass<KP, WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
   return (int)hipGetLastError();
 }
 
-template <int KP, int WK, bool VECQ>
+// PREC != 0 is instantiated for the passes with contractions only (modes 0, 1)
+template <int KP, int WK, bool VECQ, int PREC>
 int launch_fused_m(const FusedArgs& a, int mode, hipStream_t s) {
-  switch (mode) {
-    case 0: return launch_fused_t<KP, WK, VECQ, 0>(a, s);
-    case 1: return launch_fused_t<KP, WK, VECQ, 1>(a, s);
-    default: return launch_fused_t<KP, WK, VECQ, 2>(a, s);
+  if constexpr (PREC != 0) {
+    return mode == 0 ? launch_fused_t<KP, WK, VECQ, 0, PREC>(a, s) : launch_fused_t<KP, WK, VECQ, 1, PREC>(a, s);
+  } else {
+    switch (mode) {
+      case 0: return launch_fused_t<KP, WK, VECQ, 0, 0>(a, s);
+      case 1: return launch_fused_t<KP, WK, VECQ, 1, 0>(a, s);
+      default: return launch_fused_t<KP, WK, VECQ, 2, 0>(a, s);
+    }
   }
 }
 
-template <int KP, int WK>
+template <int KP, int WK, int PREC>
 int launch_fused_v(const FusedArgs& a, bool vecq, int mode, hipStream_t s) {
-  return vecq ? launch_fused_m<KP, WK, true>(a, mode, s) : launch_fused_m<KP, WK, false>(a, mode, s);
+  return vecq ? launch_fused_m<KP, WK, true, PREC>(a, mode, s) : launch_fused_m<KP, WK, false, PREC>(a, mode, s);
 }
 
-template <int KP>
+template <int KP, int PREC>
 int launch_fused_w(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
   switch (wk) {
-    case WK_KL: return launch_fused_v<KP, WK_KL>(a, vecq, mode, s);
-    case WK_EUC: return launch_fused_v<KP, WK_EUC>(a, vecq, mode, s);
-    case WK_SQRT: return launch_fused_v<KP, WK_SQRT>(a, vecq, mode, s);
-    case WK_IS: return launch_fused_v<KP, WK_IS>(a, vecq, mode, s);
-    case WK_GEN: return launch_fused_v<KP, WK_GEN>(a, vecq, mode, s);
-    case WK_RKL: return launch_fused_v<KP, WK_RKL>(a, vecq, mode, s);
-    default: return launch_fused_v<KP, WK_FAM>(a, vecq, mode, s);
+    case WK_KL: return launch_fused_v<KP, WK_KL, PREC>(a, vecq, mode, s);
+    case WK_EUC: return launch_fused_v<KP, WK_EUC, PREC>(a, vecq, mode, s);
+    case WK_SQRT: return launch_fused_v<KP, WK_SQRT, PREC>(a, vecq, mode, s);
+    case WK_IS: return launch_fused_v<KP, WK_IS, PREC>(a, vecq, mode, s);
+    case WK_GEN: return launch_fused_v<KP, WK_GEN, PREC>(a, vecq, mode, s);
+    case WK_RKL: return launch_fused_v<KP, WK_RKL, PREC>(a, vecq, mode, s);
+    default: return launch_fused_v<KP, WK_FAM, PREC>(a, vecq, mode, s);
   }
 }
 
@@ -707,10 +750,10 @@ int launch_fused_w(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t 
 template <int KP, int WK, bool VECQ, int MODE>
 int launch_fused_batched_t(const BatchedLaunch& L, hipStream_t s) {
   if (L.full)
-    hipLaunchKernelGGL((fused_pass_batched<KP, WK, VECQ, MODE, true>), dim3(L.grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((fused_pass_batched<KP, WK, VECQ, MODE, true, 0>), dim3(L.grid), dim3(256), 0, s,
                        L.args, L.work, L.n_work);
   else
-    hipLaunchKernelGGL((fused_pass_batched<KP, WK, VECQ, MODE, false>), dim3(L.grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((fused_pass_batched<KP, WK, VECQ, MODE, false, 0>), dim3(L.grid), dim3(256), 0, s,
                        L.args, L.work, L.n_work);
   return (int)hipGetLastError();
 }

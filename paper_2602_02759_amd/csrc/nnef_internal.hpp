@@ -9,6 +9,10 @@ namespace nnef {
 constexpr int kMaxPieces = 3;     // factors multiplied together to form one side row
 constexpr int kMaxEinsumIn = 4;   // inputs of one einsum step
 constexpr int kMaxEinsumLetters = 10;
+constexpr int kMaxDirectOps = 7;   // operands besides l on the direct lowering
+constexpr int kDirectKPT = 16;     // latent combinations of operand l per thread
+constexpr int kDirectMaxK = 256;   // latent combinations of operand l (16 threads x 16)
+constexpr int kDirectMaxLat = 6144;  // table entries (n_ops x K x KS) staged in LDS
 
 // Weight functions a, b (App. B), specialised by (alpha, beta).
 enum WeightKind : int {
@@ -91,6 +95,40 @@ struct FusedArgs {
   int full;                    // no ragged edges: K = KP, nqi % 16 = 0, nP % rows = 0
   int prec;                    // contraction inputs: 0 FP32, 1 BF16, 2 FP16 (width 32)
 };
+
+// Direct pass (strings with no bilinear split): for every observed entry
+// (p, q) and latent combination r of operand l,
+//   c[r] = sum_s prod_j op_j[opp_j[p] + opq_j[q] + oplat_j[r * KS + s]]
+//   yhat = sum_r theta[thp[p] + thr[r]] c[r]
+//   N[p, r] += Wa c[r],  D[p, r] += Wb c[r]
+// G threads share an entry (each a strided subset of r, combined with a
+// butterfly); a workgroup of 256 threads covers rows_per_wg rows x qlanes
+// entry groups per row over one chunk of columns and writes one partial
+// [nP][K] at slot `chunk` (the fused pass's partial layout with KP = K).
+struct DirectArgs {
+  const float* Y;              // data; with `masked`, a missing entry holds -1
+  int masked;
+  int nP, nQ;
+  const uint32_t* yp;          // [nP] Y offset of row p
+  const uint32_t* yq;          // [nQ] Y offset of column q
+  const float* theta;          // operand l
+  const uint32_t* thp;         // [nP]
+  const uint32_t* thr;         // [K]
+  int K, KS, G;
+  int n_ops;
+  const float* op[kMaxDirectOps];
+  const uint32_t* opp[kMaxDirectOps];    // [nP]
+  const uint32_t* opq[kMaxDirectOps];    // [nQ]
+  const uint32_t* oplat[kMaxDirectOps];  // [K * KS]
+  int rows_per_wg, qlanes, q_per_chunk, n_chunks, n_panels;
+  float* partN;                // [n_chunks][nP][K]
+  float* partD;
+  double* loss_part;           // [grid]
+  float alpha, beta, ab_inv, apb_inv;
+  int lk;
+  float fparam;
+};
+int launch_direct(const DirectArgs& a, int wk, int mode, void* stream);
 
 // Reduce the partials of a fused pass and apply the update (or store N_L/D_L).
 struct UpdateArgs {

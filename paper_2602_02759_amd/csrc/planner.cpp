@@ -349,6 +349,10 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
         (sd[o] == 0 ? pops : qops).push_back(t);
       }
       bp2.L_direct = pops.size() == 1 && m.ops[ell] == bp2.P + kappa;
+      // every observed letter on the row side: L would be the reconstruction
+      // itself, materialised, unless operand l is it (the direct lowering
+      // takes such blocks instead)
+      if (q_empty && !bp2.L_direct) continue;
       if (bp2.L_direct) {
         bp2.ldL = (int)K;
       } else {
@@ -479,8 +483,10 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
         }
       }
       // ---- cost: fused MFMA work on padded tiles, plus the generic contractions
-      const int rows = KP == 16 ? 64 : KP == 32 ? (kX32 ? 32 : 16 * kPT32) : 16;
-      const int qstep = (KP == 32 && kX32) ? 32 : 16;
+      // tile of the fused pass: 64 rows x 16 columns (width 16), 32 x 32 (width 32, 32x32 MFMA),
+      // 16 x 16 (width 64)
+      const int rows = KP == 16 ? 64 : KP == 32 ? 32 : 16;
+      const int qstep = KP == 32 ? 32 : 16;
       const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nqo *
                           std::ceil((double)bp2.nqi / qstep) * qstep;
       const double cost = Neff * 6.0 * KP + 16.0 * macs + 8.0 * mat_elems;
@@ -500,6 +506,131 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
   }
   bp = best;
   ws_sizes = best_ws;
+  return ST_OK;
+}
+
+std::vector<uint32_t> offsets_in(const Model& m, const std::string& letters, const std::string& subs) {
+  const std::vector<int64_t> st = row_major_strides(m, subs, 1);
+  std::vector<int64_t> sz, str;
+  for (char c : letters) {
+    sz.push_back(m.size[(unsigned char)c]);
+    const size_t pos = subs.find(c);
+    str.push_back(pos == std::string::npos ? 0 : st[pos]);
+  }
+  int64_t n = 1;
+  for (auto v : sz) n *= v;
+  std::vector<uint32_t> t((size_t)n);
+  std::vector<int64_t> idx(sz.size(), 0);
+  int64_t off = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    t[(size_t)i] = (uint32_t)off;
+    for (int d = (int)sz.size() - 1; d >= 0; --d) {
+      ++idx[d];
+      off += str[d];
+      if (idx[d] < sz[d]) break;
+      off -= sz[d] * str[d];
+      idx[d] = 0;
+    }
+  }
+  return t;
+}
+
+Status lower_direct(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>& ws_sizes,
+                    std::string& err, int target_wg) {
+  const int L = (int)m.ops.size();
+  const std::string tag = "block " + std::to_string(ell) + " ('" + m.ops[ell] + "')";
+  if (L - 1 > kMaxDirectOps) {
+    err = tag + ": the direct lowering takes at most " + std::to_string(kMaxDirectOps + 1) + " operands";
+    return ST_UNSUPPORTED;
+  }
+  BlockPlan b;
+  std::vector<int64_t> ws = ws_sizes;
+  b.ell = ell;
+  b.direct = true;
+  std::set<char> Ps;
+  std::string R;
+  for (char c : m.ops[ell]) {
+    if (m.out.find(c) != std::string::npos) Ps.insert(c);
+    else R.push_back(c);
+  }
+  b.P = letters_in_order(m.out, Ps);
+  std::set<char> Qs;
+  for (char c : m.out)
+    if (!Ps.count(c)) Qs.insert(c);
+  b.Q = letters_in_order(m.out, Qs);
+  for (char c : m.latent)
+    if (R.find(c) == std::string::npos) b.S.push_back(c);
+  b.kappa = R;
+  int64_t K = 1, KS = 1;
+  for (char c : R) K *= m.size[(unsigned char)c];
+  for (char c : b.S) KS *= m.size[(unsigned char)c];
+  if (K > kDirectMaxK || (int64_t)(L - 1) * K * KS > kDirectMaxLat) {
+    err = tag + ": the direct lowering takes at most " + std::to_string(kDirectMaxK) +
+          " latent combinations in the block's operand and " + std::to_string(kDirectMaxLat) +
+          " (other operands x latent combinations) in all; this block has " + std::to_string(K) + " and " +
+          std::to_string((int64_t)(L - 1) * K * KS);
+    return ST_UNSUPPORTED;
+  }
+  b.K = (int)K;
+  b.KP = (int)K;
+  b.KS = (int)KS;
+  b.nP = 1;
+  for (char c : b.P) b.nP *= m.size[(unsigned char)c];
+  b.nQ = 1;
+  for (char c : b.Q) b.nQ *= m.size[(unsigned char)c];
+  for (int o = 0; o < L; ++o)
+    if (o != ell) b.others.push_back(o);
+  b.ldL = (int)K;
+  b.L_direct = m.ops[ell] == b.P + R;
+  if (!b.L_direct) {  // N_L, D_L as [P][R], then permuted to operand l's layout
+    TensorRef nl;
+    nl.kind = TK_NL;
+    nl.subs = b.P + R;
+    nl.strides = row_major_strides(m, nl.subs, 1);
+    TensorRef no;
+    no.kind = TK_WS;
+    no.id = (int)ws.size();
+    no.subs = m.ops[ell];
+    no.strides = row_major_strides(m, no.subs, 1);
+    ws.push_back(no.size_of(m));
+    b.Nl_buf = no.id;
+    int64_t cb = 0;
+    b.chainN = plan_contraction(m, {nl}, no, ws, cb);
+    nl.kind = TK_DL;
+    no.id = (int)ws.size();
+    ws.push_back(no.size_of(m));
+    b.Dl_buf = no.id;
+    b.chainD = plan_contraction(m, {nl}, no, ws, cb);
+    b.NL_buf = (int)ws.size();
+    ws.push_back(b.nP * K);
+    b.DL_buf = (int)ws.size();
+    ws.push_back(b.nP * K);
+  }
+  // geometry: G threads per entry (each at most kDirectKPT latent combinations),
+  // 256 / G entry groups per workgroup split into rows x column lanes
+  int G = 1;
+  while (G * kDirectKPT < K) G *= 2;
+  b.G = G;
+  const int eg = 256 / G;
+  int ql = 1;
+  while (ql * 2 <= eg && ql * 2 <= b.nQ) ql *= 2;
+  b.qlanes = ql;
+  b.rows_per_wg = eg / ql;
+  const int64_t panels = (b.nP + b.rows_per_wg - 1) / b.rows_per_wg;
+  int64_t chunks = std::max<int64_t>(1, (target_wg + panels - 1) / panels);
+  chunks = std::min<int64_t>(chunks, (b.nQ + ql - 1) / ql);
+  const int64_t qpc = (b.nQ + chunks - 1) / chunks;
+  chunks = (b.nQ + qpc - 1) / qpc;
+  if (panels * chunks >= (int64_t(1) << 31) || b.nP >= (int64_t(1) << 31) || b.nQ >= (int64_t(1) << 31)) {
+    err = tag + ": grid too large";
+    return ST_SHAPE;
+  }
+  b.n_panels = (int)panels;
+  b.q_per_chunk = (int)qpc;
+  b.n_chunks = (int)chunks;
+  b.n_wg = (int)(panels * chunks);
+  bp = b;
+  ws_sizes = ws;
   return ST_OK;
 }
 
@@ -571,13 +702,13 @@ std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, con
 
 bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg) {
   (void)m;
-  bp.qstep = (bp.KP == 32 && kX32) ? 32 : 16;
+  bp.qstep = bp.KP == 32 ? 32 : 16;
   const int64_t nqis = (bp.nqi + bp.qstep - 1) / bp.qstep;
   bp.n_steps = bp.nqo * nqis;
   // many rows and few column steps: give each wave its own rows, so that a
   // wave runs all steps of its chunk instead of a quarter of them
-  bp.wave_rows = (bp.KP == 32 && kX32 && bp.n_steps <= 64 && bp.nP >= 4096) ? 1 : 0;
-  bp.rows = bp.KP == 16 ? 64 : bp.KP == 32 ? (kX32 ? (bp.wave_rows ? 128 : 32) : 16 * kPT32) : 16;
+  bp.wave_rows = (bp.KP == 32 && bp.n_steps <= 64 && bp.nP >= 4096) ? 1 : 0;
+  bp.rows = bp.KP == 16 ? 64 : bp.KP == 32 ? (bp.wave_rows ? 128 : 32) : 16;
   const int rows = bp.rows;
   bp.n_panels = (int)((bp.nP + rows - 1) / rows);
   const int split = bp.wave_rows ? 1 : 4;  // waves sharing a chunk's steps
@@ -617,6 +748,13 @@ bool all_zero(const std::vector<uint32_t>& t) {
 
 std::string describe_block(const Model& m, const BlockPlan& bp) {
   std::ostringstream o;
+  if (bp.direct) {
+    o << "block " << bp.ell << " '" << m.ops[bp.ell] << "': direct P={" << bp.P << "} Q={" << bp.Q
+      << "} R={" << bp.kappa << "} S={" << bp.S << "} K=" << bp.K << " KS=" << bp.KS << " nP=" << bp.nP
+      << " nQ=" << bp.nQ << " threads/entry=" << bp.G << " rows/wg=" << bp.rows_per_wg
+      << (bp.L_direct ? "" : " permute-back") << " grid=" << bp.n_wg << " chunks=" << bp.n_chunks;
+    return o.str();
+  }
   o << "block " << bp.ell << " '" << m.ops[bp.ell] << "': P={" << bp.P << "} Q={" << bp.Q
     << "} kappa={" << bp.kappa << "} K=" << bp.K << " KP=" << bp.KP << " nP=" << bp.nP
     << " nQ=" << bp.nQ << " L=" << (bp.L_direct ? "direct" : "materialised") << " R=";

@@ -8,15 +8,6 @@
 
 namespace nnef {
 
-#ifndef NNEF_PT32
-#define NNEF_PT32 2
-#endif
-constexpr int kPT32 = NNEF_PT32;  // 16-row subtiles per wave for contraction width 32
-#ifndef NNEF_X32
-#define NNEF_X32 1
-#endif
-constexpr bool kX32 = NNEF_X32 != 0;  // width 32 runs on 32x32x2 MFMA tiles (32 rows, 32-wide q steps)
-
 enum Status { ST_OK = 0, ST_PARSE = 1, ST_SHAPE = 2, ST_LOSS = 3, ST_ARG = 4, ST_DEVICE = 5,
               ST_NOMEM = 6, ST_UNSUPPORTED = 7 };
 
@@ -89,6 +80,20 @@ struct BlockPlan {
   uint32_t* d_qoyoff = nullptr;
   uint32_t* d_inbase = nullptr;    // nullptr: all zero
   uint32_t* d_orow[2] = {nullptr, nullptr};
+  // direct lowering (strings with no bilinear split of contraction width <= 64):
+  // per entry, the latent sums in registers; rows p over P = the observed letters
+  // of operand l (Y order), r over R = its latent letters (its order), s over S =
+  // the latent letters it does not hold; K = |R| (kappa = R), KS = |S|
+  bool direct = false;
+  std::string S;
+  int KS = 1;
+  int G = 1;                       // threads per entry
+  int rows_per_wg = 1, qlanes = 1, q_per_chunk = 1;
+  std::vector<int> others;         // operands other than l, in order
+  uint32_t* d_yq = nullptr;        // [nQ] Y offset of column q
+  uint32_t* d_thp = nullptr;       // [nP] offset of row p in operand l
+  uint32_t* d_thr = nullptr;       // [K] offset of latent combination r in operand l
+  std::vector<uint32_t*> d_opp, d_opq, d_oplat;
 };
 
 Status parse_model(const std::string& s, Model& m, std::string& err);
@@ -106,6 +111,14 @@ std::vector<uint32_t> inner_base_table(const Model& m, const BlockPlan& bp);
 std::vector<uint32_t> outer_row_table(const Model& m, const BlockPlan& bp, int piece);
 bool all_zero(const std::vector<uint32_t>& t);
 bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg);
+// Direct lowering of block l (see BlockPlan::direct); ST_UNSUPPORTED with a
+// message when the string is beyond its limits.
+Status lower_direct(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>& ws_sizes,
+                    std::string& err, int target_wg);
+// Element offsets into a tensor with subscripts `subs` (row-major) of every
+// multi-index over `letters` (row-major, last letter fastest); letters the
+// tensor does not hold contribute nothing.
+std::vector<uint32_t> offsets_in(const Model& m, const std::string& letters, const std::string& subs);
 std::string describe_block(const Model& m, const BlockPlan& bp);
 
 }  // namespace nnef

@@ -47,6 +47,9 @@ def _case(name):
         return datagen.tucker3(I=30, J=26, K=18, Ra=6, Rb=5, Rc=4, seed=31)
     if name == "tucker_mid":
         return datagen.tucker3(I=96, J=80, K=40, Ra=32, Rb=32, Rc=16, seed=32)
+    if name == "tucker_odd_sum":  # chain-back sums of odd length >= 64 over few tiles: the four
+        # waves of a side-contraction workgroup split the sum, the last part ragged
+        return datagen.tucker3(I=97, J=95, K=40, Ra=32, Rb=32, Rc=16, seed=35)
     if name == "tt_small":
         return datagen.tt4(I=13, J=11, K=9, Lm=7, Ra=3, Rb=4, Rc=5, seed=41)
     if name == "tt_mid":
@@ -106,13 +109,34 @@ def _case(name):
     if name == "is":
         return datagen.gamma_noise_problem("is", "ir,jr,kr->ijk", dict(i=20, j=24, k=18, r=6),
                                            1.0, -1.0, seed=66, missing=0.2)
+    # strings with no bilinear split of width <= 64 (the direct lowering)
+    if name == "manybody_gen":
+        return datagen.gamma_noise_problem("mbg", "ij,jk,ik->ijk", dict(i=23, j=19, k=21), 0.7, 0.3,
+                                           seed=74, missing=0.2)
+    if name == "manybody_rank":  # a latent letter shared by all three pairwise operands
+        return datagen.poisson_problem("mbr", "ijr,jkr,ikr->ijk", dict(i=13, j=11, k=9, r=3), 1.0, 0.0,
+                                       seed=75, truth_shape=1.0, missing=0.1)
+    if name == "permuted_direct":  # r only in the first operand, which is laid out r-first
+        return datagen.poisson_problem("pd", "rij,jk,ik->ijk", dict(i=13, j=11, k=9, r=3), 1.0, 1.0,
+                                       seed=76, truth_shape=1.0, missing=0.1)
+    if name == "row_scaling":  # every block's operand set covers all observed modes
+        return datagen.gamma_noise_problem("rs", "ij,i->ij", dict(i=30, j=20), 1.0, -1.0, seed=77,
+                                           missing=0.1)
+    if name == "cp_r70":  # rank above 64: eight threads per entry, a ragged last thread
+        return datagen.poisson_problem("cpr70", "ir,jr,kr->ijk", dict(i=21, j=19, k=17, r=70), 1.0, 0.0,
+                                       seed=78, truth_shape=0.3, missing=0.1)
+    if name == "cp_r96_is":
+        return datagen.gamma_noise_problem("cpr96", "ir,jr,kr->ijk", dict(i=15, j=13, k=11, r=96),
+                                           1.0, -1.0, seed=79, missing=0.2)
     raise KeyError(name)
 
 
 SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_gen", "tucker_small",
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
          "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full",
-         "lr_tucker", "lr_tucker_w32", "wits", "batched_side_gemm"]
+         "lr_tucker", "lr_tucker_w32", "wits", "batched_side_gemm", "manybody_gen", "manybody_rank",
+         "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is", "tucker_odd_sum"]
+DIRECT = {"manybody", "manybody_gen", "manybody_rank", "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is"}
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -121,6 +145,7 @@ def test_one_sweep_matches_oracle(name):
     print(f"[parity] {name} {p.model_str} sizes={p.sizes} ab=({p.alpha},{p.beta})", flush=True)
     plan = _plan(p)
     print(plan.describe(), flush=True)
+    assert ("direct P=" in plan.describe()) == (name in DIRECT)
     s0 = clamp_init(p)
     g1 = gpu_sweeps(plan, p, s0, 1)
     r1 = oracle_sweep(p, s0)
@@ -166,6 +191,30 @@ def test_full_size_step(name):
     print(plan.describe(), flush=True)
     s0 = clamp_init(p)
     g1 = gpu_sweeps(plan, p, s0, 1)
+    assert_step_parity(g1, oracle_sweep(p, s0), TOL, name)
+
+
+@pytest.mark.parametrize("name", ["manybody_96", "cp3_r96_128"])
+def test_full_size_direct_step(name):
+    """The direct lowering at the sizes it is meant for: the many-body string
+    at 96^3 and CP of rank 96 at 128^3 (one sweep and the loss)."""
+    if name == "manybody_96":
+        p = datagen.poisson_problem("mb96", "ij,jk,ik->ijk", dict(i=96, j=96, k=96), 1.0, 0.0, seed=80,
+                                    truth_shape=1.0, missing=0.1)
+    else:
+        p = datagen.poisson_problem("cp96", "ir,jr,kr->ijk", dict(i=128, j=128, k=128, r=96), 1.0, 0.0,
+                                    seed=81, truth_shape=0.3, missing=0.2)
+    print(f"[parity] {name} {p.model_str} {p.sizes}", flush=True)
+    plan = _plan(p)
+    desc = plan.describe()
+    print(desc, flush=True)
+    assert desc.count("direct P=") == len(p.operands)
+    s0 = clamp_init(p)
+    Y, M = to_dev(p.Y), to_dev(p.M)
+    got = plan.loss(Y, M, [to_dev(s) for s in s0])
+    ref = O.loss(p.model_str, [s.astype(np.float64) for s in s0], p.Y, p.M, p.alpha, p.beta)
+    assert abs(got - ref) <= 1e-5 * abs(ref), (got, ref)
+    g1 = gpu_sweeps(plan, p, s0, 1, Y=Y, M=M)
     assert_step_parity(g1, oracle_sweep(p, s0), TOL, name)
 
 

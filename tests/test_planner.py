@@ -19,7 +19,15 @@ def dry(*args, **kw):
 
 
 def parse(line):
-    d = {"op": re.search(r"'([a-zA-Z]+)'", line).group(1)}
+    d = {"op": re.search(r"'([a-zA-Z]+)'", line).group(1), "direct": "': direct " in line}
+    if d["direct"]:
+        for key in ("P", "Q", "R", "S"):
+            d[key] = re.search(rf"\b{key}={{([a-zA-Z]*)}}", line).group(1)
+        for key in ("K", "KS", "nP", "nQ", "grid", "chunks", "threads/entry", "rows/wg"):
+            d[key] = int(re.search(rf"\b{re.escape(key)}=(\d+)", line).group(1))
+        d["contract"] = re.search(r"contract=(\w+)", line).group(1)
+        d["permute"] = "permute-back" in line
+        return d
     for key in ("P", "Q", "kappa", "qo"):
         d[key] = re.search(rf"\b{key}={{([a-zA-Z]*)}}", line).group(1)
     for key in ("K", "KP", "nP", "nQ", "grid", "chunks", "steps/wave"):
@@ -44,17 +52,55 @@ def test_cp3_headline_lowering():
     assert b[0]["vecq"] and b[1]["vecq"] and not b[2]["vecq"]  # k is innermost in Y
 
 
-def test_manybody_takes_the_materialised_fallback():
-    for x in dry("ij,jk,ik->ijk", [19, 17, 13], [], 1.0, 0.0):
-        assert x["Q"] == "" and x["P"] == "ijk" and x["R"] == "materialised" and x["qi"] == "-"
+def test_manybody_takes_the_direct_lowering():
+    """No split of 'ij,jk,ik->ijk' keeps every operand on one side: each block
+    sums its entries directly (rows = the operand's own modes), with no
+    buffer the size of the data."""
+    b = dry("ij,jk,ik->ijk", [96, 96, 96], [], 1.0, 0.0)
+    assert all(x["direct"] for x in b)
+    assert [(x["P"], x["Q"], x["K"], x["KS"]) for x in b] == [("ij", "k", 1, 1), ("jk", "i", 1, 1),
+                                                               ("ik", "j", 1, 1)]
+    assert all(x["nP"] * x["nQ"] == 96 ** 3 and x["threads/entry"] == 1 for x in b)
+
+
+def test_rank_above_64_takes_the_direct_lowering():
+    b = dry("ir,jr,kr->ijk", [128, 128, 128], [96], 1.0, 0.0, prec="bf16")
+    assert all(x["direct"] and x["K"] == 96 and x["R"] == "r" and x["S"] == "" for x in b)
+    assert all(x["threads/entry"] == 8 and x["contract"] == "fp32" for x in b)
+
+
+def test_direct_lowering_with_other_latents_and_a_permuted_operand():
+    # r lives only in the first operand (summed there), which is laid out r-first
+    b = dry("rij,jk,ik->ijk", [13, 11, 9], [3], 1.0, 0.0)
+    assert all(x["direct"] for x in b)
+    assert (b[0]["R"], b[0]["S"], b[0]["permute"]) == ("r", "", True)
+    assert (b[1]["R"], b[1]["S"], b[1]["KS"], b[1]["permute"]) == ("", "r", 3, False)
+
+
+def test_beyond_the_direct_lowering_is_rejected():
+    from paper_2602_02759_amd.nnef import NnefError, nnef_plan_dry
+    with pytest.raises(NnefError) as e:
+        nnef_plan_dry("ir,jr,kr->ijk", [40, 30, 20], [300])
+    assert e.value.status == 7 and "direct lowering" in str(e.value)
+
+
+@pytest.mark.parametrize("model,sizes,ranks", [
+    ("ij,jk,ik->ijk", [19, 17, 13], []), ("ir,jr,kr->ijk", [40, 30, 20], [96]),
+    ("ia,jb,kc,abc->ijk", [30, 26, 18], [6, 5, 4]), ("ia,jab,kbc,lc->ijkl", [13, 11, 9, 7], [3, 4, 5]),
+    ("wr,dr,hr,irk,jrk->wdhij", [27, 7, 24, 10, 10], [10, 6]), ("ij,i->ij", [30, 20], [])])
+def test_no_block_materialises_the_reconstruction(model, sizes, ranks):
+    """No lowering holds a buffer with one value per data entry: either a
+    bilinear split with a non-empty column side, or the direct lowering."""
+    for x in dry(model, sizes, ranks, 1.0, 0.0):
+        assert x["direct"] or x["Q"] != ""
 
 
 def test_tucker_lowering_and_precision_per_width():
     b = dry("ia,jb,kc,abc->ijk", [512, 512, 128], [32, 32, 16], 1.0, -1.0, prec="bf16")
     assert [x["L"] for x in b] == ["direct", "direct", "direct", "materialised"]
     assert [x["KP"] for x in b] == [32, 32, 16, 32]
-    # BF16 contraction inputs only where the width is 32
-    assert [x["contract"] for x in b] == ["bf16", "bf16", "fp32", "bf16"]
+    # BF16 contraction inputs at every width (32x32 tiles at 32, 16x16 tiles at 16)
+    assert [x["contract"] for x in b] == ["bf16", "bf16", "bf16", "bf16"]
     assert b[3]["chain"] and b[3]["wave_rows"]          # core: 65,536 rows, 16 column steps
     assert not any(x["wave_rows"] for x in b[:3])
 
@@ -98,6 +144,7 @@ def test_geometry_invariants_on_random_cp(seed):
     dims = [int(v) for v in rng.integers(5, 300, size=3)]
     R = int(rng.choice([3, 8, 16, 24, 32, 40, 64]))
     for x in dry("ir,jr,kr->ijk", dims, [R], 1.0, 0.0):
+        assert not x["direct"]
         assert x["KP"] == (16 if R <= 16 else 32 if R <= 32 else 64) and x["K"] == R
         qstep = 32 if x["KP"] == 32 else 16
         rows = {16: 64, 32: 128 if x["wave_rows"] else 32, 64: 16}[x["KP"]]
