@@ -247,6 +247,28 @@ nnef_status nnef_mlp_train_step(nnef_mlp_t mlp, const float* X, const float* tau
                                 void* stream);
 
 /*
+ * nnef_mlp_gradient with no device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same rows, kernels and fixed-order sums
+ * as nnef_mlp_gradient, so the same gradient (float32, parameter layout) in
+ * d_grad and mean loss in *d_loss (device, may be NULL); the parameters are
+ * read from d_params (kMlpParams = nnef_mlp_num_params() float32 values,
+ * device, caller-owned) instead of an MLP handle.
+ *
+ * The per-workgroup partials live in one static device array of 18.2 MB
+ * (256 partial slots; the library never launches more workgroups for this
+ * call), held on every GPU the library runs on until the process ends.
+ * Nothing in it needs clearing (every call writes each slot it reads).
+ * Calls that overlap on one GPU (two streams, two threads) share the array
+ * and race: serialise them.  Enqueue only; no host synchronisation.
+ * Errors: NNEF_E_ARG for NULL pointers or n_rows <= 0, NNEF_E_SHAPE for
+ * n_rows >= 2^31, NNEF_E_DEVICE if the array's address cannot be obtained.
+ */
+nnef_status nnef_mlp_gradient_noalloc(const float* d_params, const float* X, const float* tau,
+                                      const int32_t* idx, int64_t n_rows, float* d_grad,
+                                      double* d_loss, void* stream);
+
+/*
  * Training rows from a multiplicative-update trajectory of `plan`'s model:
  * for every factor element (factors concatenated in operand order), the eight
  * features above into X [numel_total][8], and, when th_target (theta_{t+h})

@@ -31,6 +31,12 @@ int env_int(const char* name, int dflt) {
 }
 }  // namespace
 
+// Error reporting for entry points defined in other translation units.
+namespace nnef {
+nnef_status report_error(nnef_status st, const std::string& msg) { return fail(st, msg); }
+nnef_status report_hip_error(int e, const char* what) { return hip_fail(e, what); }
+}  // namespace nnef
+
 struct nnef_plan_s {
   Model m;
   LossSpec ls;

@@ -107,6 +107,9 @@ EXPORTS = {
     "nnef_mlp_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "nnef_mlp_gradient_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p]),
     "nnef_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                            ctypes.c_void_p, ctypes.c_void_p]),
@@ -291,6 +294,15 @@ def nnef_mlp_gradient(h, X, tau, idx, n_rows, d_grad, d_loss=None, stream=None):
                                    _ptr(idx, torch.int32, "idx"), int(n_rows),
                                    _ptr(d_grad, torch.float32, "d_grad"),
                                    _ptr(d_loss, torch.float64, "d_loss"), _stream(stream)))
+
+
+def nnef_mlp_gradient_noalloc(params, X, tau, idx, n_rows, d_grad, d_loss=None, stream=None):
+    import torch
+    _check(lib().nnef_mlp_gradient_noalloc(_ptr(params, torch.float32, "params"),
+                                           _ptr(X, torch.float32, "X"), _ptr(tau, torch.float32, "tau"),
+                                           _ptr(idx, torch.int32, "idx"), int(n_rows),
+                                           _ptr(d_grad, torch.float32, "d_grad"),
+                                           _ptr(d_loss, torch.float64, "d_loss"), _stream(stream)))
 
 
 def nnef_mlp_train_step(h, X, tau, idx, n_rows, lr, d_loss=None, stream=None):
