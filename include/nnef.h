@@ -401,8 +401,12 @@ void nnef_default_fit_options(nnef_fit_options* opt);
  * rules are checked, and otherwise one sweep is run on the training entries.
  * train_trace / val_trace (device, may be NULL) receive the losses of
  * theta_0 .. theta_{stop_sweep}; they need room for max_sweeps + 1 doubles.
- * Allocates a packed copy of the validation data for the call and
- * synchronises the stream.
+ * One packed copy of the data (the plan's packing buffer) holds both splits,
+ * and the two losses of theta_t come from the first fused pass of sweep t + 1
+ * (no separate loss passes); the factors of the last state of every chunk of
+ * check_every states are kept on the device, so a stop there returns exactly
+ * that state.  Allocates those small buffers for the call and synchronises the
+ * stream once per chunk.
  */
 nnef_status nnef_fit(nnef_plan_t plan, const float* Y, const uint8_t* mask, float* const* factors,
                      const nnef_fit_options* opt, nnef_fit_result* res, double* train_trace,

@@ -18,10 +18,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnnef.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "learned.hip", "fused16.hip", "fused32.hip", "fused64.hip", "fused16bf.hip",
-           "fused16h.hip", "fused64bf.hip", "fused64h.hip",
-           "fused16b.hip", "fused32b.hip", "fused64b.hip", "noalloc.hip", "direct.hip", "planner.cpp",
-           "abi.cpp"]
+SOURCES = ["kernels.hip", "learned.hip", "fused16.hip", "fused16bf.hip", "fused16h.hip", "fused32.hip",
+           "fused32bf.hip", "fused32h.hip", "fused64.hip", "fused64bf.hip", "fused64h.hip", "fused16b.hip",
+           "fused32b.hip", "fused64b.hip", "noalloc.hip", "direct.hip", "planner.cpp", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel

@@ -49,6 +49,7 @@ struct nnef_plan_s {
   float* partN = nullptr;
   float* partD = nullptr;
   double* loss_part = nullptr;
+  double* vloss_part = nullptr;    // validation-entry loss partials (split packs)
   double* loss_tmp = nullptr;
   float* dcol = nullptr;
   float* ypack = nullptr;          // data with missing entries stored as -1
@@ -91,6 +92,7 @@ static void free_plan(nnef_plan_s* p) {
   if (p->partN) (void)hipFree(p->partN);
   if (p->partD) (void)hipFree(p->partD);
   if (p->loss_part) (void)hipFree(p->loss_part);
+  if (p->vloss_part) (void)hipFree(p->vloss_part);
   if (p->loss_tmp) (void)hipFree(p->loss_tmp);
   if (p->dcol) (void)hipFree(p->dcol);
   if (p->ypack) (void)hipFree(p->ypack);
@@ -268,6 +270,7 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
   if (hipMalloc((void**)&p->partN, std::max<size_t>(1, part_elems) * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&p->partD, std::max<size_t>(1, part_elems) * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&p->loss_part, std::max(1, p->max_wg) * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->vloss_part, std::max(1, p->max_wg) * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&p->loss_tmp, sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&p->dcol, 64 * sizeof(float)) != hipSuccess ||
       (with_pack && hipMalloc((void**)&p->ypack, (size_t)N * sizeof(float)) != hipSuccess)) {
@@ -504,9 +507,10 @@ static int run_side_prep(const nnef_plan_s* p, const BlockPlan& bp, const float*
 }
 
 // One sweep of Algorithm 1 over packed data; loss_slot (device, may be null)
-// receives the loss at the start of the sweep.
+// receives the loss at the start of the sweep, vloss_slot (device, may be
+// null; needs loss_slot) the loss of the validation entries of a split pack.
 static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float* const* factors,
-                             double* loss_slot, hipStream_t s) {
+                             double* loss_slot, hipStream_t s, double* vloss_slot = nullptr) {
   const int L = (int)p->m.ops.size();
   const float* const* cf = factors;
   for (int l = 0; l < L; ++l) {
@@ -520,6 +524,7 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
       if (e) return hip_fail(e, "side-operand contraction launch");
       fa = fused_args(p, bp, Yd, masked, cf);
       fa.loss_part = want_loss ? p->loss_part : nullptr;
+      fa.vloss_part = want_loss && vloss_slot ? p->vloss_part : nullptr;
     }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (p->timing) {
@@ -530,6 +535,7 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
     if (bp.direct) {
       DirectArgs da = direct_args(p, bp, Yd, masked, cf);
       da.loss_part = want_loss ? p->loss_part : nullptr;
+      da.vloss_part = want_loss && vloss_slot ? p->vloss_part : nullptr;
       e = launch_direct(da, p->ls.wk, want_loss ? 1 : 0, s);
     } else {
       e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, want_loss ? 1 : 0, s);
@@ -564,6 +570,10 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
     if (want_loss) {
       ua.loss_part = p->loss_part;
       ua.n_loss_part = bp.n_wg;
+      if (vloss_slot) {
+        ua.vloss_part = p->vloss_part;
+        ua.vloss_out = vloss_slot;
+      }
       ua.loss_out = loss_slot;
     }
     e = launch_update(ua, p->dcol, s);
@@ -587,24 +597,28 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
   return NNEF_OK;
 }
 
-// The loss of the given factors over packed data, into d_loss (device).
+// The loss of the given factors over packed data, into d_loss (device); with
+// d_vloss (device) also the loss of the validation entries of a split pack.
 static nnef_status run_loss(nnef_plan_s* p, const float* Yd, bool masked, const float* const* factors,
-                            double* d_loss, hipStream_t s) {
+                            double* d_loss, hipStream_t s, double* d_vloss = nullptr) {
   const BlockPlan& bp = p->blocks[0];
   int e = 0;
   if (bp.direct) {
     DirectArgs da = direct_args(p, bp, Yd, masked, factors);
     da.loss_part = p->loss_part;
+    da.vloss_part = d_vloss ? p->vloss_part : nullptr;
     e = launch_direct(da, p->ls.wk, 2, s);
   } else {
     e = run_side_prep(p, bp, factors, s);
     if (e) return hip_fail(e, "side-operand contraction launch");
     FusedArgs fa = fused_args(p, bp, Yd, masked, factors);
     fa.loss_part = p->loss_part;
+    fa.vloss_part = d_vloss ? p->vloss_part : nullptr;
     e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, 2, s);
   }
   if (e) return hip_fail(e, "loss pass launch");
   e = launch_loss_final(p->loss_part, bp.n_wg, d_loss, s);
+  if (!e && d_vloss) e = launch_loss_final(p->vloss_part, bp.n_wg, d_vloss, s);
   if (e) return hip_fail(e, "loss reduction launch");
   return NNEF_OK;
 }
@@ -725,38 +739,54 @@ nnef_status nnef_fit(nnef_plan_t p, const float* Y, const uint8_t* M, float* con
     return fail(NNEF_E_ARG, "invalid fit options");
   hipStream_t s = (hipStream_t)stream;
   const bool use_val = o.val_value != 0;
-  // per state: training and validation losses (device), read back in chunks
+  const int L = (int)p->m.ops.size();
+  // One pack holds both splits: training entries as data, validation entries
+  // with the sign bit set.  The losses of state t (training and validation)
+  // come from the first fused pass of sweep t + 1, which streams Y anyway; the
+  // factors of the last state of each chunk are kept, so that a stop there
+  // returns exactly that state.
   const int k = o.check_every;
-  float* yval = nullptr;
-  double* dl = nullptr;
-  if ((use_val && hipMalloc((void**)&yval, (size_t)p->n_data * sizeof(float)) != hipSuccess) ||
-      hipMalloc((void**)&dl, 2 * (size_t)k * sizeof(double)) != hipSuccess) {
-    if (yval) (void)hipFree(yval);
+  double* dl = nullptr;   // [2k] losses of the chunk's states
+  float* snap = nullptr;  // the factors of the chunk's last state
+  if (hipMalloc((void**)&dl, 2 * (size_t)k * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&snap, (size_t)std::max<int64_t>(1, p->numel_total) * sizeof(float)) != hipSuccess) {
+    if (dl) (void)hipFree(dl);
     return fail(NNEF_E_NOMEM, "fit buffers");
   }
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(s);
-    if (yval) (void)hipFree(yval);
     (void)hipFree(dl);
+    (void)hipFree(snap);
   };
-  int e = launch_pack(Y, M, p->ypack, p->n_data, s, o.train_value);
-  if (!e && use_val) e = launch_pack(Y, M, yval, p->n_data, s, o.val_value);
+  auto copy_factors = [&](bool to_snap) -> bool {
+    int64_t off = 0;
+    for (int l = 0; l < L; ++l) {
+      float* a = snap + off;
+      const hipError_t e = to_snap ? hipMemcpyAsync(a, factors[l], p->numel[l] * sizeof(float),
+                                                    hipMemcpyDeviceToDevice, s)
+                                   : hipMemcpyAsync(factors[l], a, p->numel[l] * sizeof(float),
+                                                    hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return false;
+      off += p->numel[l];
+    }
+    return true;
+  };
+  int e = launch_pack(Y, M, p->ypack, p->n_data, s, o.train_value, use_val ? o.val_value : 256);
   if (e) {
     cleanup();
     return hip_fail(e, "data packing launch");
   }
-  std::vector<double> L, V, hl(2 * (size_t)k);
-  int run = 0, stop = -1, reason = NNEF_STOP_MAX;
+  std::vector<double> Lh, Vh, hl(2 * (size_t)k);
+  int stop = -1, reason = NNEF_STOP_MAX, returned = 0;
   for (int s0 = 0; stop < 0; s0 += k) {
     const int cnt = std::min(k, o.max_sweeps - s0 + 1);
-    // states s0 .. s0 + cnt - 1: losses of each, a sweep between consecutive ones
+    // sweep j of the chunk yields the losses of state s0 + j
     for (int j = 0; j < cnt; ++j) {
-      if (j > 0) {
-        st = run_sweep(p, p->ypack, true, factors, nullptr, s);
-        if (st == NNEF_OK) ++run;
+      if (j == cnt - 1 && !copy_factors(true)) {
+        cleanup();
+        return fail(NNEF_E_DEVICE, "factor snapshot failed");
       }
-      if (st == NNEF_OK) st = run_loss(p, p->ypack, true, factors, dl + j, s);
-      if (st == NNEF_OK && use_val) st = run_loss(p, yval, true, factors, dl + k + j, s);
+      st = run_sweep(p, p->ypack, true, factors, dl + j, s, use_val ? dl + k + j : nullptr);
       if (st != NNEF_OK) {
         cleanup();
         return st;
@@ -769,16 +799,16 @@ nnef_status nnef_fit(nnef_plan_t p, const float* Y, const uint8_t* M, float* con
     }
     for (int j = 0; j < cnt && stop < 0; ++j) {
       const int t = s0 + j;
-      L.push_back(hl[j]);
-      V.push_back(use_val ? hl[k + j] : 0.0);
+      Lh.push_back(hl[j]);
+      Vh.push_back(use_val ? hl[k + j] : 0.0);
       // the paper's rules: validation loss rising `patience` times in a row,
       // relative decrease of the training loss below rel_tol, or the sweep cap
       bool rising = use_val && o.patience > 0 && t >= o.patience;
-      for (int q = 0; rising && q < o.patience; ++q) rising = V[t - q] > V[t - q - 1];
+      for (int q = 0; rising && q < o.patience; ++q) rising = Vh[t - q] > Vh[t - q - 1];
       if (rising) {
         stop = t;
         reason = NNEF_STOP_VALIDATION;
-      } else if (t >= 1 && (L[t - 1] - L[t]) < o.rel_tol * std::fabs(L[t - 1])) {
+      } else if (t >= 1 && (Lh[t - 1] - Lh[t]) < o.rel_tol * std::fabs(Lh[t - 1])) {
         stop = t;
         reason = NNEF_STOP_TRAIN_TOL;
       } else if (t >= o.max_sweeps) {
@@ -786,26 +816,27 @@ nnef_status nnef_fit(nnef_plan_t p, const float* Y, const uint8_t* M, float* con
         reason = NNEF_STOP_MAX;
       }
     }
-    if (stop < 0) {  // advance to the first state of the next chunk
-      st = run_sweep(p, p->ypack, true, factors, nullptr, s);
-      if (st != NNEF_OK) {
+    if (stop >= 0) {  // back to the chunk's last state (the stopping state when check_every = 1)
+      if (!copy_factors(false)) {
         cleanup();
-        return st;
+        return fail(NNEF_E_DEVICE, "factor restore failed");
       }
-      ++run;
+      returned = s0 + cnt - 1;
     }
   }
-  if (train_trace && hipMemcpyAsync(train_trace, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+  if (train_trace && hipMemcpyAsync(train_trace, Lh.data(), (size_t)(stop + 1) * sizeof(double),
+                                    hipMemcpyHostToDevice, s) != hipSuccess)
     st = fail(NNEF_E_DEVICE, "trace copy failed");
   if (val_trace && use_val &&
-      hipMemcpyAsync(val_trace, V.data(), V.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+      hipMemcpyAsync(val_trace, Vh.data(), (size_t)(stop + 1) * sizeof(double), hipMemcpyHostToDevice, s) !=
+          hipSuccess)
     st = fail(NNEF_E_DEVICE, "trace copy failed");
   cleanup();
   res->stop_sweep = stop;
-  res->sweeps_run = run;
+  res->sweeps_run = returned;
   res->reason = reason;
-  res->train_loss = L[stop];
-  res->val_loss = use_val ? V[stop] : 0.0;
+  res->train_loss = Lh[stop];
+  res->val_loss = use_val ? Vh[stop] : 0.0;
   return st;
 }
 

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void direct_pass(DirectArgs a) {
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
   __shared__ uint32_t slat[kDirectMaxLat];
   __shared__ float red[ND ? 256 * KPT : 1];
-  __shared__ double lred[4];
+  __shared__ double lred[8];
   const int tid = threadIdx.x;
   const int G = a.G;
   const int gi = tid & (G - 1), eg = tid / G;
@@ -60,13 +60,14 @@ __global__ __launch_bounds__(256) void direct_pass(DirectArgs a) {
 #pragma unroll
   for (int j = 0; j < kMaxDirectOps; ++j) pb[j] = (j < nops && pval) ? a.opp[j][p] : 0u;
 
-  double lsum = 0.0;
+  double lsum = 0.0, vsum = 0.0;
+  const bool vmode = LOSS && a.vloss_part != nullptr;
   const int q0 = chunk * a.q_per_chunk;
   const int q1 = min(a.nQ, q0 + a.q_per_chunk);
   for (int q = q0 + ql; q < q1; q += a.qlanes) {
-    const float yv = pval ? ldf(a.Y, yrow + a.yq[q]) : -1.f;
-    // rows past the end and (with a mask) missing entries hold -1
-    const bool obs = (!a.masked && pval) || yv >= 0.f;
+    const float yv = pval ? ldf(a.Y, yrow + a.yq[q]) : -INFINITY;
+    // rows past the end and (with a mask) missing entries are negative
+    const bool obs = (!a.masked && pval) || observed(yv);
     uint32_t qb[kMaxDirectOps];
 #pragma unroll
     for (int j = 0; j < kMaxDirectOps; ++j) qb[j] = j < nops ? pb[j] + a.opq[j][q] : 0u;
@@ -104,15 +105,27 @@ __global__ __launch_bounds__(256) void direct_pass(DirectArgs a) {
       }
     }
     if constexpr (LOSS) {
-      if (gi == 0 && obs) lsum += (double)ab_loss<WK>(y, yhat, fa);
+      const bool val = vmode && validation(yv);
+      if (gi == 0 && (obs || val)) {
+        const double l = (double)ab_loss<WK>(obs ? y : -yv, yhat, fa);
+        if (obs) lsum += l;
+        else vsum += l;
+      }
     }
   }
 
   if constexpr (LOSS) {
     const double w = wave_sum(lsum);
     if ((tid & 63) == 0) lred[tid >> 6] = w;
+    if (vmode) {
+      const double wv = wave_sum(vsum);
+      if ((tid & 63) == 0) lred[4 + (tid >> 6)] = wv;
+    }
     __syncthreads();
-    if (tid == 0) a.loss_part[blockIdx.x] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+    if (tid == 0) {
+      a.loss_part[blockIdx.x] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+      if (vmode) a.vloss_part[blockIdx.x] = ((lred[4] + lred[5]) + lred[6]) + lred[7];
+    }
   }
   if constexpr (ND) {
     // thread tid = ((ql * rows_per_wg + rl) * G + gi) holds r = gi + G i of its

@@ -3,5 +3,5 @@
 #include "fused_x32.hpp"
 
 namespace nnef {
-int launch_fused_batched_kp32(const BatchedLaunch& L, hipStream_t s) { return launch_x32_batched(L, s); }
+int launch_fused_batched_kp32(const BatchedLaunch& L, hipStream_t s) { return launch_x32_batched<1>(L, s); }
 }  // namespace nnef

@@ -1,0 +1,8 @@
+// Fused-pass instantiations for contraction width 32 with FP16 contraction inputs.
+#include "fused_x32.hpp"
+
+namespace nnef {
+int launch_fused_kp32_fp16(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
+  return launch_x32<1, 2>(a, wk, vecq, mode, s);
+}
+}  // namespace nnef

@@ -1,8 +1,8 @@
 // Fused-pass instantiations for contraction width 64 with FP16 contraction inputs.
-#include "fused_impl.hpp"
+#include "fused_x32.hpp"
 
 namespace nnef {
 int launch_fused_kp64_fp16(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
-  return launch_fused_w<64, 2>(a, wk, vecq, mode, s);
+  return launch_x32<2, 2>(a, wk, vecq, mode, s);
 }
 }  // namespace nnef

@@ -64,6 +64,12 @@ __device__ __forceinline__ f4 mfma4_lp(const float (&av)[4], const f4& bv, f4 c)
   }
 }
 
+// Packed data hold an observed value with its sign bit clear (data are
+// nonnegative); a validation entry of a split as the value with the sign bit
+// set (-0 for a zero), everything else (missing entries, tile padding) as -inf.
+__device__ __forceinline__ bool observed(float yv) { return __builtin_bit_cast(int, yv) >= 0; }
+__device__ __forceinline__ bool validation(float yv) { return !observed(yv) && yv != -INFINITY; }
+
 // Loads at a 32-bit element offset from a wave-uniform base pointer.  The
 // offset is turned into a 32-bit byte offset so that the compiler can address
 // through the scalar base (no 64-bit address arithmetic per lane); every
@@ -336,7 +342,7 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
   constexpr int PT = T::PT, ROWS = T::ROWS, KS = T::KS, KT = T::KT, RST = T::RST;
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
   __shared__ f4 red4[ND ? 3 * ROWS * RST / 4 : 1];
-  __shared__ double lred[4];
+  __shared__ double lred[8];
   float* red = reinterpret_cast<float*>(red4);
 
   const int lane = threadIdx.x & 63;
@@ -373,7 +379,7 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
       accN[t][kt] = f4{0.f, 0.f, 0.f, 0.f};
       accD[t][kt] = f4{0.f, 0.f, 0.f, 0.f};
     }
-  double lsum = 0.0;
+  double lsum = 0.0, vsum = 0.0;
 
   // ---- outer factors: u[k] = prod_m outer_m[orow_m[qo]][k] is folded into the
   // row operand (Lu = L * u) for the reconstruction, and into the contraction
@@ -509,7 +515,7 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
         const bool ok = FULL || (pval[t] && q4 < a.nqi);
         const int q4c = FULL ? q4 : (q4 < a.nqi ? q4 : a.nqi - 4);
         const f4 v = ldf4(a.Y, ybase + poff[t] + (uint32_t)q4c);
-        d.y[t] = ok ? v : f4{-1.f, -1.f, -1.f, -1.f};
+        d.y[t] = ok ? v : f4{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -517,13 +523,14 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
           const bool ok = FULL || (pval[t] && q < a.nqi);
           const int qc = FULL ? q : (q < a.nqi ? q : a.nqi - 1);
           const float v = ldf(a.Y, ybase + poff[t] + (uint32_t)qc * qys);
-          d.y[t][r] = ok ? v : -1.f;
+          d.y[t][r] = ok ? v : -INFINITY;
         }
       }
     }
   };
 
   const bool masked = a.masked != 0;  // else every entry is observed (y >= 0 by contract)
+  const bool vmode = LOSS && a.vloss_part != nullptr;
   // One step: reconstruction R(t), weights W(t), contractions ND(t) for the
   // p subtiles t, ordered R(0) R(1)|W(0) ND(0)|W(1) ND(1) ... so that the
   // weight arithmetic of one subtile issues in the shadow of the MFMAs of
@@ -538,9 +545,9 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float yv = ym.y[t][r];
-      // ragged tiles pad out-of-range entries with -1 as well: they count as
+      // ragged tiles pad out-of-range entries with -inf as well: they count as
       // missing whether or not the caller passed a mask
-      const bool obs = (FULL && !masked) || yv >= 0.f;
+      const bool obs = (FULL && !masked) || observed(yv);
       const float y = (masked || !FULL) ? fmaxf(yv, 0.f) : yv;
       const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[r], FLT_MIN, FLT_MAX) : yh[r];
       if constexpr (ND) {
@@ -551,8 +558,10 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
         wb[r] = obs ? xb : 0.f;
       }
       if constexpr (LOSS) {
-        const float l = ab_loss<WK>(obs ? y : 1.f, obs ? yhat : 1.f, a);
+        const bool val = vmode && validation(yv);
+        const float l = ab_loss<WK>(obs ? y : (val ? -yv : 1.f), (obs || val) ? yhat : 1.f, a);
         lsum += obs ? (double)l : 0.0;
+        vsum += val ? (double)l : 0.0;
       }
     }
   };
@@ -678,8 +687,15 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
   if constexpr (LOSS) {
     const double w = wave_sum(lsum);
     if (lane == 0) lred[wave] = w;
+    if (vmode) {  // uniform: the split pack's validation entries
+      const double wv = wave_sum(vsum);
+      if (lane == 0) lred[4 + wave] = wv;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) a.loss_part[slot] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+    if (threadIdx.x == 0) {
+      a.loss_part[slot] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+      if (vmode) a.vloss_part[slot] = ((lred[4] + lred[5]) + lred[6]) + lred[7];
+    }
   }
   if constexpr (ND) {
     store_partial<KP>(accN, a.partN, red, a, wave, g, c, p0, chunk);

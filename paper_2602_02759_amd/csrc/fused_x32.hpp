@@ -1,9 +1,13 @@
-// Fused pass for contraction width 32 on v_mfma_f32_32x32x2_f32.
+// Fused pass for contraction widths 32 (NT = 1) and 64 (NT = 2) on
+// v_mfma_f32_32x32x2_f32.
 //
 // Same computation as fused_pass in fused_impl.hpp (one block update's pass
 // over Y: reconstruction tile, masked (alpha, beta) weights, numerator and
 // denominator contractions), with 32 x 32 tiles: this MFMA form sustains the
-// full FP32 matrix rate of the chip, the 16x16x4 form does not.
+// full FP32 matrix rate of the chip, the 16x16x4 form does not.  The
+// contraction width is NT tiles of 32: the reconstruction sums all of them
+// into one 32 x 32 tile, and N, D keep one accumulator tile each per kappa
+// tile (width 64 runs one wave per SIMD to hold them without spills).
 //
 // MFMA layout (32x32x2): lane l = 32*g + c supplies A[row c][k g] and
 // B[k g][col c]; the accumulator register v holds C[row 8(v/4) + 4g + v%4][col c].
@@ -53,9 +57,9 @@ __device__ __forceinline__ f16v mfma_lp(const float* av, const float* bv, const 
 // (0 = FP32, 1 = BF16, 2 = FP16); the reconstruction is always FP32.
 // One workgroup's tile: braw is the workgroup index within the problem's
 // grid (before the XCD remap), slot its loss-partial index.
-template <int WK, bool VECQ, int MODE, bool FULL, int PREC>
+template <int NT, int WK, bool VECQ, int MODE, bool FULL, int PREC>
 __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int slot) {
-  constexpr int KP = 32, ROWS = 32, RST = KP + 4;
+  constexpr int KP = 32 * NT, ROWS = 32, RST = KP + 4;
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
   // Y ring for the direct-to-LDS prefetch of full tiles: kStages stages of 4 KB
   // per wave; after the main loop the same memory holds the partial reduction.
@@ -63,7 +67,7 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   constexpr int kRing = FULL ? 4 * kStages * 256 : 0;     // f4 elements
   constexpr int kRed = ND ? 3 * ROWS * RST / 4 : 1;       // f4 elements
   __shared__ f4 lds4[kRing > kRed ? kRing : kRed];
-  __shared__ double lred[4];
+  __shared__ double lred[8];
   float* red = reinterpret_cast<float*>(lds4);
 
   // Every argument the prologue reads, requested in one batch: left to
@@ -99,43 +103,58 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   const bool pval = FULL || p < a.nP;
   const uint32_t poff = pval ? a.p_off[p] : 0u;
   const bool masked = a.masked != 0;
+  const bool vmode = LOSS && a.vloss_part != nullptr;
 
-  f16v accN = {}, accD = {};
-  double lsum = 0.0;
-
-  // ---- per-qo state: Lu[s] = L[p][16g + s] * u[16g + s] (reconstruction B operand),
-  // ul = u[c] (scales the contraction A operand, whose row is k = c)
-  float Lu[16];
-  float ul = 1.f;
-  auto set_u = [&](int qo) {
-    float uA[16];
+  f16v accN[NT], accD[NT];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) uA[s] = 1.f;
-    ul = 1.f;
+  for (int t = 0; t < NT; ++t) {
+    accN[t] = f16v{};
+    accD[t] = f16v{};
+  }
+  double lsum = 0.0, vsum = 0.0;
+
+  // ---- per-qo state: Lu[t][s] = L[p][32t + 16g + s] * u[32t + 16g + s]
+  // (reconstruction B operand), ul[t] = u[32t + c] (scales the contraction A
+  // operand of kappa tile t, whose row is k = 32t + c)
+  float Lu[NT][16];
+  float ul[NT];
+  auto set_u = [&](int qo) {
+    float uA[NT][16];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) uA[t][s] = 1.f;
+      ul[t] = 1.f;
+    }
     for (int m = 0; m < a.nouter; ++m) {
       const float* ob = a.outer[m];
       const uint32_t roff = a.orow[m][qo] * (uint32_t)a.ld_out[m];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) uA[s] *= ldf(ob, roff + min(16 * g + s, a.K - 1));
-      ul *= ldf(ob, roff + min(c, a.K - 1));
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) uA[t][s] *= ldf(ob, roff + min(32 * t + 16 * g + s, a.K - 1));
+        ul[t] *= ldf(ob, roff + min(32 * t + c, a.K - 1));
+      }
     }
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int k = 16 * g + s;
-      const float lv = (pval && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
-      Lu[s] = lv * uA[s];
-    }
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int k = 32 * t + 16 * g + s;
+        const float lv = (pval && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
+        Lu[t][s] = lv * uA[t][s];
+      }
   };
 
   // ---- column side of one step (raw inner rows).  Every load is a
   // wave-uniform pointer plus a loop-invariant lane offset, so a step's
   // addressing is scalar arithmetic only.
   struct Cols {
-    float Ra[16];  // C[qi0 + c][16g + s]             (A of the reconstruction)
-    float Rb[16];  // C[qi0 + 8(v/4) + 4g + v%4][c]   (A of N and D, MFMA step v)
+    float Ra[NT][16];  // C[qi0 + c][32t + 16g + s]             (A of the reconstruction)
+    float Rb[NT][16];  // C[qi0 + 8(v/4) + 4g + v%4][32t + c]   (A of N and D, MFMA step v)
   };
   const uint32_t ld_in = (uint32_t)a.ld_in, in_stride = (uint32_t)a.in_stride;
-  // full tiles: inner rows are 32 floats apart (K = ld = 32, in_stride = 1), so
+  // full tiles: inner rows are KP floats apart (K = ld = KP, in_stride = 1), so
   // every offset inside a step is a compile-time immediate on one base pointer
   const uint32_t offA = (uint32_t)c * KP + 16u * g;         // lane part of Ra addresses
   const uint32_t offB = (uint32_t)(4 * g) * KP + (uint32_t)c;  // lane part of Rb addresses
@@ -143,41 +162,53 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
     if constexpr (FULL) {
       const float* base = a.inner + (size_t)(ibase + (uint32_t)qi0) * KP;
 #pragma unroll
-      for (int s = 0; s < 16; s += 4) {
-        const f4 v = ldf4(base, offA + s);
-        d.Ra[s] = v[0];
-        d.Ra[s + 1] = v[1];
-        d.Ra[s + 2] = v[2];
-        d.Ra[s + 3] = v[3];
-      }
+      for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) d.Rb[v] = ldf(base, offB + (uint32_t)(8 * (v >> 2) + (v & 3)) * KP);
+        for (int s = 0; s < 16; s += 4) {
+          const f4 v = ldf4(base, offA + 32 * t + s);
+          d.Ra[t][s] = v[0];
+          d.Ra[t][s + 1] = v[1];
+          d.Ra[t][s + 2] = v[2];
+          d.Ra[t][s + 3] = v[3];
+        }
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          d.Rb[t][v] = ldf(base, offB + 32 * t + (uint32_t)(8 * (v >> 2) + (v & 3)) * KP);
     } else {
       const int qa = qi0 + c;
       const bool va = qa < a.nqi;
       const uint32_t ra = (ibase + (uint32_t)(va ? qa : a.nqi - 1) * in_stride) * ld_in;
       if (a.K == KP && (ld_in & 3u) == 0) {  // full-width rows: float4 loads
 #pragma unroll
-        for (int s = 0; s < 16; s += 4) {
-          const f4 v = ldf4(a.inner, ra + 16u * g + s);
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) d.Ra[s + j] = va ? v[j] : 0.f;
-        }
+          for (int s = 0; s < 16; s += 4) {
+            const f4 v = ldf4(a.inner, ra + 32u * t + 16u * g + s);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) d.Ra[t][s + j] = va ? v[j] : 0.f;
+          }
       } else {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const int k = 16 * g + s;
-          const float v = ldf(a.inner, ra + (uint32_t)min(k, a.K - 1));
-          d.Ra[s] = (va && k < a.K) ? v : 0.f;
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const int k = 32 * t + 16 * g + s;
+            const float v = ldf(a.inner, ra + (uint32_t)min(k, a.K - 1));
+            d.Ra[t][s] = (va && k < a.K) ? v : 0.f;
+          }
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int qb = qi0 + 8 * (v >> 2) + 4 * g + (v & 3);
-        const bool vb = qb < a.nqi && c < a.K;
-        const float x = ldf(a.inner, (ibase + (uint32_t)(qb < a.nqi ? qb : a.nqi - 1) * in_stride) * ld_in +
-                                         (uint32_t)min(c, a.K - 1));
-        d.Rb[v] = vb ? x : 0.f;
+        const uint32_t rb = (ibase + (uint32_t)(qb < a.nqi ? qb : a.nqi - 1) * in_stride) * ld_in;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bool vb = qb < a.nqi && 32 * t + c < a.K;
+          const float x = ldf(a.inner, rb + (uint32_t)min(32 * t + c, a.K - 1));
+          d.Rb[t][v] = vb ? x : 0.f;
+        }
       }
     }
   };
@@ -200,7 +231,7 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
           const bool ok = pval && q4 < a.nqi;
           const int q4c = q4 < a.nqi ? q4 : a.nqi - 4;
           const f4 v = ldf4(a.Y, ybase + poff + (uint32_t)q4c);
-          d.y[bq] = ok ? v : f4{-1.f, -1.f, -1.f, -1.f};
+          d.y[bq] = ok ? v : f4{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
         }
       } else {
 #pragma unroll
@@ -211,7 +242,7 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
           } else {
             const bool ok = pval && q < a.nqi;
             const float v = ldf(a.Y, ybase + poff + (uint32_t)(q < a.nqi ? q : a.nqi - 1) * qys);
-            d.y[bq][r] = ok ? v : -1.f;
+            d.y[bq][r] = ok ? v : -INFINITY;
           }
         }
       }
@@ -258,15 +289,17 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   auto compute = [&](const YM& ym, const Cols& cl) {
     f16v yh = {};
 #pragma unroll
-    for (int s = 0; s < 16; ++s) yh = mfma32(cl.Ra[s], Lu[s], yh);
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < 16; ++s) yh = mfma32(cl.Ra[t][s], Lu[t][s], yh);
     f16v wa, wb;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float yv = ym.y[v >> 2][v & 3];
-      // ragged tiles pad out-of-range entries with -1 as well: they count as
+      // ragged tiles pad out-of-range entries with -inf as well: they count as
       // missing whether or not the caller passed a mask
-      const bool obs = (FULL && !masked) || yv >= 0.f;
-      // a missing entry (-1) becomes 0: a(0, yhat) = 0 for alpha > 0
+      const bool obs = (FULL && !masked) || observed(yv);
+      // a missing entry (negative) becomes 0: a(0, yhat) = 0 for alpha > 0
       const float y = (masked || !FULL) ? __builtin_amdgcn_fmed3f(yv, 0.f, FLT_MAX) : yv;
       const float yhat = needs_floor<WK>() ? __builtin_amdgcn_fmed3f(yh[v], FLT_MIN, FLT_MAX) : yh[v];
       if constexpr (ND) {
@@ -277,34 +310,39 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
         wb[v] = obs ? xb : 0.f;
       }
       if constexpr (LOSS) {
-        const float l = ab_loss<WK>(obs ? y : 1.f, obs ? yhat : 1.f, a);
+        const bool val = vmode && validation(yv);
+        const float l = ab_loss<WK>(obs ? y : (val ? -yv : 1.f), (obs || val) ? yhat : 1.f, a);
         lsum += obs ? (double)l : 0.0;
+        vsum += val ? (double)l : 0.0;
       }
     }
     if constexpr (ND) {
-      // N^T[k][p] += sum_q (u[k] C[q][k]) W^T[q][p]
-      float rb[16];
+      // N^T[k][p] += sum_q (u[k] C[q][k]) W^T[q][p], one accumulator tile per kappa tile
 #pragma unroll
-      for (int v = 0; v < 16; ++v) rb[v] = cl.Rb[v] * ul;
-      if constexpr (PREC == 0) {
+      for (int t = 0; t < NT; ++t) {
+        float rb[16];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) accN = mfma32(rb[v], wa[v], accN);
-        if (!a.no_d) {
+        for (int v = 0; v < 16; ++v) rb[v] = cl.Rb[t][v] * ul[t];
+        if constexpr (PREC == 0) {
 #pragma unroll
-          for (int v = 0; v < 16; ++v) accD = mfma32(rb[v], wb[v], accD);
-        }
-      } else {
-        float wav[16], wbv[16];
+          for (int v = 0; v < 16; ++v) accN[t] = mfma32(rb[v], wa[v], accN[t]);
+          if (!a.no_d) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          wav[v] = wa[v];
-          wbv[v] = wb[v];
-        }
-        accN = mfma_lp<PREC>(rb, wav, accN);
-        accN = mfma_lp<PREC>(rb + 8, wav + 8, accN);
-        if (!a.no_d) {
-          accD = mfma_lp<PREC>(rb, wbv, accD);
-          accD = mfma_lp<PREC>(rb + 8, wbv + 8, accD);
+            for (int v = 0; v < 16; ++v) accD[t] = mfma32(rb[v], wb[v], accD[t]);
+          }
+        } else {
+          float wav[16], wbv[16];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            wav[v] = wa[v];
+            wbv[v] = wb[v];
+          }
+          accN[t] = mfma_lp<PREC>(rb, wav, accN[t]);
+          accN[t] = mfma_lp<PREC>(rb + 8, wav + 8, accN[t]);
+          if (!a.no_d) {
+            accD[t] = mfma_lp<PREC>(rb, wbv, accD[t]);
+            accD[t] = mfma_lp<PREC>(rb + 8, wbv + 8, accD[t]);
+          }
         }
       }
     }
@@ -340,7 +378,11 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
     if constexpr (!FULL) set_u(q0);
   } else {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) Lu[s] = 0.f;
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) Lu[t][s] = 0.f;
+      ul[t] = 1.f;
+    }
   }
   if constexpr (FULL) {
    if (nst > 0) {
@@ -348,7 +390,7 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
     // one step ahead.  Issue order per step: Y DMA (nY ops), then column loads
     // (nC ops).  Before reading stage j at least kWait ops issued after its DMA
     // exist in every non-tail step, so vmcnt <= kWait implies it landed.
-    constexpr int nY = VECQ ? 4 : 16, nC = 4 + 16;
+    constexpr int nY = VECQ ? 4 : 16, nC = NT * (4 + 16);
     constexpr int kMin = (kStages - 1) * nY + 2 * nC < nC + (kStages - 1) * (nY + nC)
                              ? (kStages - 1) * nY + 2 * nC
                              : nC + (kStages - 1) * (nY + nC);
@@ -439,38 +481,52 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   if constexpr (LOSS) {
     const double w = wave_sum(lsum);
     if (lane == 0) lred[wave] = w;
+    if (vmode) {  // uniform: the split pack's validation entries
+      const double wv = wave_sum(vsum);
+      if (lane == 0) lred[4 + wave] = wv;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) a.loss_part[slot] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+    if (threadIdx.x == 0) {
+      a.loss_part[slot] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+      if (vmode) a.vloss_part[slot] = ((lred[4] + lred[5]) + lred[6]) + lred[7];
+    }
   }
   if constexpr (ND) {
-    // accumulator register v holds X^T[k = 8(v/4) + 4g + v%4][p = p0 + c]; waves
-    // 1..3 stash theirs, wave 0 adds them in a fixed order and stores the partial
-    auto store = [&](const f16v& acc, float* dst) {
+    // accumulator register v of tile t holds X^T[k = 32t + 8(v/4) + 4g + v%4][p = p0 + c];
+    // waves 1..3 stash theirs, wave 0 adds them in a fixed order and stores the partial
+    auto store = [&](const f16v (&acc)[NT], float* dst) {
       if (wrows) {  // each wave owns its rows
         if (p < a.nP) {
 #pragma unroll
-          for (int bq = 0; bq < 4; ++bq)
-            *reinterpret_cast<f4*>(&dst[((size_t)chunk * a.nP + p) * KP + 8 * bq + 4 * g]) =
-                f4{acc[4 * bq], acc[4 * bq + 1], acc[4 * bq + 2], acc[4 * bq + 3]};
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int bq = 0; bq < 4; ++bq)
+              *reinterpret_cast<f4*>(&dst[((size_t)chunk * a.nP + p) * KP + 32 * t + 8 * bq + 4 * g]) =
+                  f4{acc[t][4 * bq], acc[t][4 * bq + 1], acc[t][4 * bq + 2], acc[t][4 * bq + 3]};
         }
         return;
       }
       if (wave > 0) {
 #pragma unroll
-        for (int bq = 0; bq < 4; ++bq)
-          *reinterpret_cast<f4*>(&red[(wave - 1) * ROWS * RST + c * RST + 8 * bq + 4 * g]) =
-              f4{acc[4 * bq], acc[4 * bq + 1], acc[4 * bq + 2], acc[4 * bq + 3]};
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int bq = 0; bq < 4; ++bq)
+            *reinterpret_cast<f4*>(&red[(wave - 1) * ROWS * RST + c * RST + 32 * t + 8 * bq + 4 * g]) =
+                f4{acc[t][4 * bq], acc[t][4 * bq + 1], acc[t][4 * bq + 2], acc[t][4 * bq + 3]};
       }
       __syncthreads();
       if (wave == 0) {
 #pragma unroll
-        for (int bq = 0; bq < 4; ++bq) {
-          f4 v = f4{acc[4 * bq], acc[4 * bq + 1], acc[4 * bq + 2], acc[4 * bq + 3]};
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-          for (int w = 0; w < 3; ++w)
-            v += *reinterpret_cast<const f4*>(&red[w * ROWS * RST + c * RST + 8 * bq + 4 * g]);
-          if (p < a.nP) *reinterpret_cast<f4*>(&dst[((size_t)chunk * a.nP + p) * KP + 8 * bq + 4 * g]) = v;
-        }
+          for (int bq = 0; bq < 4; ++bq) {
+            f4 v = f4{acc[t][4 * bq], acc[t][4 * bq + 1], acc[t][4 * bq + 2], acc[t][4 * bq + 3]};
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+              v += *reinterpret_cast<const f4*>(&red[w * ROWS * RST + c * RST + 32 * t + 8 * bq + 4 * g]);
+            if (p < a.nP)
+              *reinterpret_cast<f4*>(&dst[((size_t)chunk * a.nP + p) * KP + 32 * t + 8 * bq + 4 * g]) = v;
+          }
       }
       __syncthreads();
     };
@@ -479,106 +535,112 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   }
 }
 
-template <int WK, bool VECQ, int MODE, bool FULL, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_x32(
-    FusedArgs a) {
-  fused_x32_body<WK, VECQ, MODE, FULL, PREC>(a, blockIdx.x, blockIdx.x);
+// Width 32 runs two waves per SIMD; width 64 holds twice the accumulators and
+// column operands and runs one (its registers then include the accumulation
+// registers, so nothing spills).
+template <int NT, int WK, bool VECQ, int MODE, bool FULL, int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 2 : 1, NT == 1 ? 2 : 1))) void
+fused_x32(FusedArgs a) {
+  fused_x32_body<NT, WK, VECQ, MODE, FULL, PREC>(a, blockIdx.x, blockIdx.x);
 }
 
 // Persistent form over many problems: work item w = (problem, workgroup index
 // in that problem's grid); each workgroup walks the items w = blockIdx.x,
 // blockIdx.x + gridDim.x, ...
-template <int WK, bool VECQ, int MODE, bool FULL, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_x32_batched(
-    const FusedArgs* __restrict__ args, const WorkItem* __restrict__ work, int n_work) {
+template <int NT, int WK, bool VECQ, int MODE, bool FULL, int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 2 : 1, NT == 1 ? 2 : 1))) void
+fused_x32_batched(const FusedArgs* __restrict__ args, const WorkItem* __restrict__ work, int n_work) {
   for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
     const WorkItem it = work[w];
     const FusedArgs a = args[it.run];
-    fused_x32_body<WK, VECQ, MODE, FULL, PREC>(a, it.blk, it.blk);
+    fused_x32_body<NT, WK, VECQ, MODE, FULL, PREC>(a, it.blk, it.blk);
     __syncthreads();
   }
 }
 
 #ifndef NNEF_BATCHED_TU
-template <int WK, bool VECQ, int MODE, int PREC>
+template <int NT, int WK, bool VECQ, int MODE, int PREC>
 int launch_x32_p(const FusedArgs& a, hipStream_t s) {
   if (a.full)
-    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((fused_x32<NT, WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((fused_x32<WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((fused_x32<NT, WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
   return (int)hipGetLastError();
 }
 
-template <int WK, bool VECQ, int MODE>
-int launch_x32_t(const FusedArgs& a, hipStream_t s) {
-  if (MODE == 2 || a.prec == 0) return launch_x32_p<WK, VECQ, MODE, 0>(a, s);  // the loss pass has no contraction
-  if (a.prec == 1) return launch_x32_p<WK, VECQ, MODE, 1>(a, s);
-  return launch_x32_p<WK, VECQ, MODE, 2>(a, s);
-}
-
-template <int WK>
-int launch_x32_w(const FusedArgs& a, bool vecq, int mode, hipStream_t s) {
-  if (vecq) {
+// PREC != 0 is instantiated for the passes with contractions only (modes 0, 1)
+template <int NT, int WK, bool VECQ, int PREC>
+int launch_x32_m(const FusedArgs& a, int mode, hipStream_t s) {
+  if constexpr (PREC != 0) {
+    return mode == 0 ? launch_x32_p<NT, WK, VECQ, 0, PREC>(a, s) : launch_x32_p<NT, WK, VECQ, 1, PREC>(a, s);
+  } else {
     switch (mode) {
-      case 0: return launch_x32_t<WK, true, 0>(a, s);
-      case 1: return launch_x32_t<WK, true, 1>(a, s);
-      default: return launch_x32_t<WK, true, 2>(a, s);
+      case 0: return launch_x32_p<NT, WK, VECQ, 0, 0>(a, s);
+      case 1: return launch_x32_p<NT, WK, VECQ, 1, 0>(a, s);
+      default: return launch_x32_p<NT, WK, VECQ, 2, 0>(a, s);
     }
   }
-  switch (mode) {
-    case 0: return launch_x32_t<WK, false, 0>(a, s);
-    case 1: return launch_x32_t<WK, false, 1>(a, s);
-    default: return launch_x32_t<WK, false, 2>(a, s);
-  }
 }
 
+template <int NT, int WK, int PREC>
+int launch_x32_v(const FusedArgs& a, bool vecq, int mode, hipStream_t s) {
+  return vecq ? launch_x32_m<NT, WK, true, PREC>(a, mode, s) : launch_x32_m<NT, WK, false, PREC>(a, mode, s);
+}
+
+// One contraction width and input precision: the weight kind, data layout and
+// mode are dispatched at run time.
+template <int NT, int PREC>
 int launch_x32(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
   switch (wk) {
-    case WK_KL: return launch_x32_w<WK_KL>(a, vecq, mode, s);
-    case WK_EUC: return launch_x32_w<WK_EUC>(a, vecq, mode, s);
-    case WK_SQRT: return launch_x32_w<WK_SQRT>(a, vecq, mode, s);
-    case WK_IS: return launch_x32_w<WK_IS>(a, vecq, mode, s);
-    case WK_GEN: return launch_x32_w<WK_GEN>(a, vecq, mode, s);
-    case WK_RKL: return launch_x32_w<WK_RKL>(a, vecq, mode, s);
-    default: return launch_x32_w<WK_FAM>(a, vecq, mode, s);
+    case WK_KL: return launch_x32_v<NT, WK_KL, PREC>(a, vecq, mode, s);
+    case WK_EUC: return launch_x32_v<NT, WK_EUC, PREC>(a, vecq, mode, s);
+    case WK_SQRT: return launch_x32_v<NT, WK_SQRT, PREC>(a, vecq, mode, s);
+    case WK_IS: return launch_x32_v<NT, WK_IS, PREC>(a, vecq, mode, s);
+    case WK_GEN: return launch_x32_v<NT, WK_GEN, PREC>(a, vecq, mode, s);
+    case WK_RKL: return launch_x32_v<NT, WK_RKL, PREC>(a, vecq, mode, s);
+    default: return launch_x32_v<NT, WK_FAM, PREC>(a, vecq, mode, s);
   }
 }
 
 #else
-template <int WK, bool VECQ, int MODE, int PREC>
+template <int NT, int WK, bool VECQ, int MODE, int PREC>
 int launch_x32_batched_p(const BatchedLaunch& L, hipStream_t s) {
   if (L.full)
-    hipLaunchKernelGGL((fused_x32_batched<WK, VECQ, MODE, true, PREC>), dim3(L.grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((fused_x32_batched<NT, WK, VECQ, MODE, true, PREC>), dim3(L.grid), dim3(256), 0, s,
                        L.args, L.work, L.n_work);
   else
-    hipLaunchKernelGGL((fused_x32_batched<WK, VECQ, MODE, false, PREC>), dim3(L.grid), dim3(256), 0,
+    hipLaunchKernelGGL((fused_x32_batched<NT, WK, VECQ, MODE, false, PREC>), dim3(L.grid), dim3(256), 0,
                        s, L.args, L.work, L.n_work);
   return (int)hipGetLastError();
 }
 
-template <int WK, bool VECQ, int MODE>
+template <int NT, int WK, bool VECQ, int MODE>
 int launch_x32_batched_m(const BatchedLaunch& L, hipStream_t s) {
-  if (L.prec == 0) return launch_x32_batched_p<WK, VECQ, MODE, 0>(L, s);
-  if (L.prec == 1) return launch_x32_batched_p<WK, VECQ, MODE, 1>(L, s);
-  return launch_x32_batched_p<WK, VECQ, MODE, 2>(L, s);
+  if constexpr (NT == 1) {
+    if (L.prec == 1) return launch_x32_batched_p<NT, WK, VECQ, MODE, 1>(L, s);
+    if (L.prec == 2) return launch_x32_batched_p<NT, WK, VECQ, MODE, 2>(L, s);
+  }
+  return launch_x32_batched_p<NT, WK, VECQ, MODE, 0>(L, s);
 }
 
-template <int WK>
+template <int NT, int WK>
 int launch_x32_batched_w(const BatchedLaunch& L, hipStream_t s) {
   if (L.vecq)
-    return L.mode ? launch_x32_batched_m<WK, true, 1>(L, s) : launch_x32_batched_m<WK, true, 0>(L, s);
-  return L.mode ? launch_x32_batched_m<WK, false, 1>(L, s) : launch_x32_batched_m<WK, false, 0>(L, s);
+    return L.mode ? launch_x32_batched_m<NT, WK, true, 1>(L, s) : launch_x32_batched_m<NT, WK, true, 0>(L, s);
+  return L.mode ? launch_x32_batched_m<NT, WK, false, 1>(L, s) : launch_x32_batched_m<NT, WK, false, 0>(L, s);
 }
 
+// Batched passes: width 32 (NT = 1) in every input precision, width 64 in FP32.
+template <int NT>
 int launch_x32_batched(const BatchedLaunch& L, hipStream_t s) {
   switch (L.wk) {
-    case WK_KL: return launch_x32_batched_w<WK_KL>(L, s);
-    case WK_EUC: return launch_x32_batched_w<WK_EUC>(L, s);
-    case WK_SQRT: return launch_x32_batched_w<WK_SQRT>(L, s);
-    case WK_IS: return launch_x32_batched_w<WK_IS>(L, s);
-    case WK_GEN: return launch_x32_batched_w<WK_GEN>(L, s);
-    case WK_RKL: return launch_x32_batched_w<WK_RKL>(L, s);
-    default: return launch_x32_batched_w<WK_FAM>(L, s);
+    case WK_KL: return launch_x32_batched_w<NT, WK_KL>(L, s);
+    case WK_EUC: return launch_x32_batched_w<NT, WK_EUC>(L, s);
+    case WK_SQRT: return launch_x32_batched_w<NT, WK_SQRT>(L, s);
+    case WK_IS: return launch_x32_batched_w<NT, WK_IS>(L, s);
+    case WK_GEN: return launch_x32_batched_w<NT, WK_GEN>(L, s);
+    case WK_RKL: return launch_x32_batched_w<NT, WK_RKL>(L, s);
+    default: return launch_x32_batched_w<NT, WK_FAM>(L, s);
   }
 }
 

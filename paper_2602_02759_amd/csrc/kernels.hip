@@ -133,6 +133,12 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dc
     for (int i = lane; i < a.n_loss_part; i += 64) sl += a.loss_part[i];
     sl = wave_sum(sl);
     if (lane == 0) *a.loss_out = sl;
+    if (a.vloss_out) {
+      double sv = 0.0;
+      for (int i = lane; i < a.n_loss_part; i += 64) sv += a.vloss_part[i];
+      sv = wave_sum(sv);
+      if (lane == 0) *a.vloss_out = sv;
+    }
   }
 }
 
@@ -173,6 +179,12 @@ __global__ __launch_bounds__(256) void update_flat_kernel(UpdateArgs a, const fl
     for (int i = (int)threadIdx.x; i < a.n_loss_part; i += 64) sl += a.loss_part[i];
     sl = wave_sum(sl);
     if (threadIdx.x == 0) *a.loss_out = sl;
+    if (a.vloss_out) {
+      double sv = 0.0;
+      for (int i = (int)threadIdx.x; i < a.n_loss_part; i += 64) sv += a.vloss_part[i];
+      sv = wave_sum(sv);
+      if (threadIdx.x == 0) *a.vloss_out = sv;
+    }
   }
 }
 
@@ -371,9 +383,14 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
 
 // Missing entries become -1 (observed data are nonnegative); the value stored
 // at a missing entry is never read into arithmetic, only replaced.
+__device__ __forceinline__ float pack_one(float y, uint32_t m, uint32_t value, uint32_t vvalue) {
+  return m == value ? y : (m == vvalue ? __builtin_copysignf(y, -1.f) : -INFINITY);
+}
+
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Y,
                                                    const uint8_t* __restrict__ M,
-                                                   float* __restrict__ Yp, int64_t n, uint32_t value) {
+                                                   float* __restrict__ Yp, int64_t n, uint32_t value,
+                                                   uint32_t vvalue) {
   typedef float v4 __attribute__((ext_vector_type(4)));
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i + 3 < n) {
@@ -381,10 +398,10 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Y,
     const uint32_t m = *reinterpret_cast<const uint32_t*>(M + i);
     v4 o;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) o[j] = ((m >> (8 * j)) & 0xffu) == value ? y[j] : -1.f;
+    for (int j = 0; j < 4; ++j) o[j] = pack_one(y[j], (m >> (8 * j)) & 0xffu, value, vvalue);
     *reinterpret_cast<v4*>(Yp + i) = o;
   } else {
-    for (int64_t j = i; j < n; ++j) Yp[j] = M[j] == value ? Y[j] : -1.f;
+    for (int64_t j = i; j < n; ++j) Yp[j] = pack_one(Y[j], M[j], value, vvalue);
   }
 }
 
@@ -699,11 +716,11 @@ int launch_loss_final(const double* part, int n, double* out, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream, int value) {
+int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream, int value, int vvalue) {
   if (n <= 0) return 0;
   const int64_t threads = (n + 3) / 4;
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, Y, M, Yp, n, (uint32_t)value);
+                     (hipStream_t)stream, Y, M, Yp, n, (uint32_t)value, (uint32_t)vvalue);
   return (int)hipGetLastError();
 }
 

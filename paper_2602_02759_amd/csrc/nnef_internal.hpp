@@ -87,6 +87,7 @@ struct FusedArgs {
   float* partN;                // [n_chunks][nP][KP]
   float* partD;                // [n_chunks][nP][KP] (unused when no_d)
   double* loss_part;           // [n_wg] (loss passes)
+  double* vloss_part;          // [n_wg] or null: also the loss of the validation entries (split pack)
   int no_d;                    // D is a closed form (b = 1, no mask): skip it
   float alpha, beta;           // for WK_GEN and the generic loss
   float ab_inv, apb_inv;       // 1/(alpha*beta), 1/(alpha+beta)
@@ -124,6 +125,7 @@ struct DirectArgs {
   float* partN;                // [n_chunks][nP][K]
   float* partD;
   double* loss_part;           // [grid]
+  double* vloss_part;          // [grid] or null (validation entries of a split pack)
   float alpha, beta, ab_inv, apb_inv;
   int lk;
   float fparam;
@@ -144,8 +146,9 @@ struct UpdateArgs {
   float* theta; int ldT;       // theta[p*ldT + k]
   float* NL; float* DL;        // [nP][K] when chaining back (theta == nullptr)
   int upd; float gamma; float eps;
-  // loss finalisation (first block of a sweep)
+  // loss finalisation (first block of a sweep); vloss: validation entries of a split pack
   const double* loss_part; int n_loss_part; double* loss_out;
+  const double* vloss_part; double* vloss_out;
   float* dcol;                 // [K] closed-form D scratch (no_d)
 };
 
@@ -197,8 +200,12 @@ int launch_apply(const ApplyArgs& a, void* stream);
 int launch_loss_final(const double* part, int n, double* out, void* stream);
 int launch_zero(float* p, int64_t n, void* stream);
 int launch_copy_f64(double* dst, const double* src, int n, void* stream);
-// Yp[i] = mask[i] == value ? Y[i] : -1 (observed data are nonnegative).
-int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream, int value = 1);
+// Packed data: Yp[i] = Y[i] where mask[i] == value (observed; data are
+// nonnegative, so the sign bit is clear), -Y[i] with the sign bit set (-0 for
+// a zero) where mask[i] == vvalue (a validation entry of a split), -inf
+// elsewhere.  vvalue outside 0..255: no validation entries.
+int launch_pack(const float* Y, const uint8_t* M, float* Yp, int64_t n, void* stream, int value = 1,
+                int vvalue = 256);
 
 // ---- learned extrapolation (a small MLP over per-element trajectory features)
 constexpr int kMlpIn = 8, kMlpWidth = 128;

@@ -483,10 +483,10 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
         }
       }
       // ---- cost: fused MFMA work on padded tiles, plus the generic contractions
-      // tile of the fused pass: 64 rows x 16 columns (width 16), 32 x 32 (width 32, 32x32 MFMA),
-      // 16 x 16 (width 64)
-      const int rows = KP == 16 ? 64 : KP == 32 ? 32 : 16;
-      const int qstep = KP == 32 ? 32 : 16;
+      // tile of the fused pass: 64 rows x 16 columns (width 16, 16x16 MFMA), 32 x 32 (widths 32
+      // and 64, 32x32 MFMA)
+      const int rows = KP == 16 ? 64 : 32;
+      const int qstep = KP == 16 ? 16 : 32;
       const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nqo *
                           std::ceil((double)bp2.nqi / qstep) * qstep;
       const double cost = Neff * 6.0 * KP + 16.0 * macs + 8.0 * mat_elems;
@@ -702,13 +702,13 @@ std::vector<uint32_t> piece_rows_table(const Model& m, const std::string& Q, con
 
 bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg) {
   (void)m;
-  bp.qstep = bp.KP == 32 ? 32 : 16;
+  bp.qstep = bp.KP == 16 ? 16 : 32;
   const int64_t nqis = (bp.nqi + bp.qstep - 1) / bp.qstep;
   bp.n_steps = bp.nqo * nqis;
   // many rows and few column steps: give each wave its own rows, so that a
   // wave runs all steps of its chunk instead of a quarter of them
-  bp.wave_rows = (bp.KP == 32 && bp.n_steps <= 64 && bp.nP >= 4096) ? 1 : 0;
-  bp.rows = bp.KP == 16 ? 64 : bp.KP == 32 ? (bp.wave_rows ? 128 : 32) : 16;
+  bp.wave_rows = (bp.KP != 16 && bp.n_steps <= 64 && bp.nP >= 4096) ? 1 : 0;
+  bp.rows = bp.KP == 16 ? 64 : (bp.wave_rows ? 128 : 32);
   const int rows = bp.rows;
   bp.n_panels = (int)((bp.nP + rows - 1) / rows);
   const int split = bp.wave_rows ? 1 : 4;  // waves sharing a chunk's steps

@@ -77,6 +77,12 @@ def _case(name):
         return datagen.poisson_problem("icews_tall", "ir,jr,ak,kr,tr->ijat",
                                        dict(i=40, j=40, a=10, t=12, r=32, k=4), 1.0, 1.0, seed=68,
                                        truth_shape=0.5, missing=0.1)
+    if name == "icews_tall_r64":  # width 64 (32x32 tiles, two kappa tiles) with one row panel per wave
+        return datagen.poisson_problem("icews_tall_r64", "ir,jr,ak,kr,tr->ijat",
+                                       dict(i=40, j=40, a=10, t=12, r=64, k=4), 1.0, 0.0, seed=82,
+                                       truth_shape=0.5, missing=0.1)
+    if name == "cp3_full_r64":
+        return datagen.cp3(1.0, 1.0, R=64)
     if name == "icews_tall_full":  # the same on full tiles
         return datagen.poisson_problem("icews_tall_full", "ir,jr,ak,kr,tr->ijat",
                                        dict(i=64, j=64, a=8, t=16, r=32, k=4), 1.0, 0.0, seed=69,
@@ -135,7 +141,7 @@ SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_ge
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
          "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full",
          "lr_tucker", "lr_tucker_w32", "wits", "batched_side_gemm", "manybody_gen", "manybody_rank",
-         "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is", "tucker_odd_sum"]
+         "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is", "tucker_odd_sum", "icews_tall_r64"]
 DIRECT = {"manybody", "manybody_gen", "manybody_rank", "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is"}
 
 
@@ -169,9 +175,10 @@ def test_loss_matches_oracle(name):
     assert abs(got - ref) <= 1e-5 * abs(ref), (got, ref)
 
 
-@pytest.mark.parametrize("name", ["cp3_full_euc", "cp3_full_ab"])
+@pytest.mark.parametrize("name", ["cp3_full_euc", "cp3_full_ab", "cp3_full_r64"])
 def test_full_size_cp3_step(name):
-    """The benchmark workload: CP 256^3, R = 32, 20 % missing, one sweep."""
+    """The benchmark workload: CP 256^3, R = 32, 20 % missing, one sweep (and
+    the same at R = 64, the width-64 pass on full tiles)."""
     p = _case(name)
     print(f"[parity] {name}", flush=True)
     plan = _plan(p)
@@ -287,3 +294,32 @@ def test_deterministic_and_resumable():
     c = gpu_sweeps(plan, p, gpu_sweeps(plan, p, s0, 1), 2)
     for x, y in zip(a, c):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("name", ["icews", "uber400"])
+def test_paper_shape_sweep_against_stored_oracle(name):
+    """The ICEWS string at 249 x 249 x 20 x 228 (283 M entries) and the Uber
+    string at the 400 x 400 mesh (726 M entries): one GPU sweep from the seeded
+    init against the FP64 oracle's sweep, which is too large to run inside the
+    test and was stored by tests/golden/make_big_sweeps.py (oracle only); the
+    loss before and after the sweep at 1e-5."""
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_sweep1.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} has not been written")
+    ref = np.load(path)
+    p = datagen.icews_problem() if name == "icews" else datagen.uber_problem(mesh=400)
+    print(f"[parity] {name} {p.model_str} {p.sizes}", flush=True)
+    plan = _plan(p)
+    print(plan.describe(), flush=True)
+    Y, M = to_dev(p.Y), to_dev(p.M)
+    f = [to_dev(s) for s in clamp_init(p)]
+    l0 = plan.loss(Y, M, f)
+    assert abs(l0 - float(ref["loss0"])) <= 1e-5 * float(ref["loss0"]), (l0, float(ref["loss0"]))
+    plan.step(Y, M, f, n_sweeps=1)
+    torch.cuda.synchronize()
+    g1 = [t.cpu().numpy() for t in f]
+    assert_step_parity(g1, [ref[f"f{i}"] for i in range(len(g1))], TOL, name)
+    l1 = plan.loss(Y, M, f)
+    assert abs(l1 - float(ref["loss1"])) <= 1e-5 * float(ref["loss1"]), (l1, float(ref["loss1"]))

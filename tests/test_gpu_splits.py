@@ -66,8 +66,30 @@ def test_fit_matches_oracle(opts):
             "validation": O.STOP_VALIDATION}[res["reason"]] == rr
     assert abs(res["stop_sweep"] - rt) <= 2
     m = min(res["stop_sweep"], rt) + 1
-    np.testing.assert_allclose(tt.cpu().numpy()[:m], L[:m], rtol=1e-4)
-    np.testing.assert_allclose(tv.cpu().numpy()[:m], V[:m], rtol=1e-4)
+    np.testing.assert_allclose(tt.cpu().numpy()[:m], L[:m], rtol=1e-5)
+    np.testing.assert_allclose(tv.cpu().numpy()[:m], V[:m], rtol=1e-5)
     assert res["sweeps_run"] >= res["stop_sweep"]
     if opts.get("check_every", 1) == 1:
         assert res["sweeps_run"] == res["stop_sweep"]
+        # the returned factors are the stopping state itself
+        fs = [x.cpu().numpy().astype(np.float64) for x in f]
+        lt = O.loss(p.model_str, fs, p.Y, (M == 1).astype(np.uint8), p.alpha, p.beta)
+        assert abs(lt - res["train_loss"]) <= 1e-5 * lt
+
+
+def test_fit_losses_equal_the_split_loss_passes():
+    """The training and validation losses nnef_fit takes from the fused pass
+    of the following sweep (one pack holding both splits) equal the separate
+    loss passes over each split of the same state."""
+    import torch
+    p, M = _problem()
+    plan = _plan(p)
+    Y, Md = to_dev(p.Y), to_dev(M)
+    f = [to_dev(s) for s in clamp_init(p)]
+    tt = torch.zeros(6, dtype=torch.float64, device="cuda")
+    tv = torch.zeros(6, dtype=torch.float64, device="cuda")
+    res = plan.fit(Y, Md, f, tt, tv, max_sweeps=5, rel_tol=0.0, patience=0)
+    assert res["stop_sweep"] == 5 and res["reason"] == "max_sweeps" and res["sweeps_run"] == 5
+    for value, tr in ((1, tt), (2, tv)):
+        sep = plan.loss_split(Y, Md, value, f)
+        assert abs(tr[5].item() - sep) <= 1e-6 * sep, (value, tr[5].item(), sep)

@@ -146,8 +146,8 @@ def test_geometry_invariants_on_random_cp(seed):
     for x in dry("ir,jr,kr->ijk", dims, [R], 1.0, 0.0):
         assert not x["direct"]
         assert x["KP"] == (16 if R <= 16 else 32 if R <= 32 else 64) and x["K"] == R
-        qstep = 32 if x["KP"] == 32 else 16
-        rows = {16: 64, 32: 128 if x["wave_rows"] else 32, 64: 16}[x["KP"]]
+        qstep = 16 if x["KP"] == 16 else 32
+        rows = 64 if x["KP"] == 16 else (128 if x["wave_rows"] else 32)
         panels = math.ceil(x["nP"] / rows)
         assert x["grid"] == panels * x["chunks"]
         nqi = {"i": dims[0], "j": dims[1], "k": dims[2]}[x["qi"]]
