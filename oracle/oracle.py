@@ -383,6 +383,65 @@ def sweep(model_str, factors, Y, M, alpha, beta, eps, block_losses=None):
     return f
 
 
+def _slab_bounds(n, n_slabs):
+    return [(int(a), int(b)) for a, b in zip(np.linspace(0, n, n_slabs + 1)[:-1],
+                                              np.linspace(0, n, n_slabs + 1)[1:]) if b > a]
+
+
+def _slab_factors(model_str, factors, a, b):
+    """The factors restricted to entries whose first observed index lies in [a, b)."""
+    m = parse_model(model_str)
+    c = m.output[0]
+    out = []
+    for t, f in zip(m.operands, factors):
+        if c in t:
+            idx = [slice(None)] * len(t)
+            idx[t.index(c)] = slice(a, b)
+            f = f[tuple(idx)]
+        out.append(f)
+    return out
+
+
+def loss_slabs(model_str, factors, Y, M, alpha, beta, n_slabs) -> float:
+    """``loss`` summed slab by slab along the first observed mode (eq. 3.1 is a
+    sum over entries), for tensors too large to reconstruct at once."""
+    tot = 0.0
+    for a, b in _slab_bounds(np.shape(Y)[0], n_slabs):
+        fs = _slab_factors(model_str, factors, a, b)
+        tot += loss(model_str, fs, Y[a:b], None if M is None else M[a:b], alpha, beta)
+    return tot
+
+
+def sweep_slabs(model_str, factors, Y, M, alpha, beta, eps, n_slabs):
+    """``sweep`` with the reconstruction and the numerator and denominator
+    einsums of every block evaluated slab by slab along the first observed mode
+    (the sums over entries in eqs. 2.1 and 3.6 are additive; an operand that
+    holds that mode receives each slab's rows, the others the sum over slabs).
+    The same update up to summation order, for tensors too large to hold the
+    reconstruction and its weights at once."""
+    m = parse_model(model_str)
+    c = m.output[0]
+    f = [np.asarray(t, dtype=np.float64) for t in factors]
+    for ell in range(len(f)):
+        N = np.zeros(f[ell].shape)
+        D = np.zeros(f[ell].shape)
+        t = m.operands[ell]
+        for a, b in _slab_bounds(np.shape(Y)[0], n_slabs):
+            fs = _slab_factors(model_str, f, a, b)
+            n_, d_ = numerator_denominator(model_str, fs, ell, Y[a:b], None if M is None else M[a:b],
+                                           alpha, beta)
+            if c in t:
+                idx = [slice(None)] * len(t)
+                idx[t.index(c)] = slice(a, b)
+                N[tuple(idx)] = n_
+                D[tuple(idx)] = d_
+            else:
+                N += n_
+                D += d_
+        f[ell] = apply_update(f[ell], N, D, alpha, beta, eps)
+    return f
+
+
 def fit(model_str, factors, Y, M, alpha, beta, eps=1e-10, n_sweeps=1,
         trace=False):
     """Algorithm 1 for a fixed number of sweeps, from max(eps, Theta_init).

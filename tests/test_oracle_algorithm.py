@@ -261,3 +261,24 @@ def test_kkt_residual_floor_reached_by_mu():
     f = O.fit("ir,jr->ij", f, Y, None, 1.0, 0.0, 1e-10, n_sweeps=2000)
     assert np.all(f[0][2] == 1e-10)
     assert O.kkt_residual("ir,jr->ij", f, Y, None, 1.0, 0.0, 1e-10) < 1e-4
+
+
+@pytest.mark.parametrize("model_str,sizes,ab", [
+    ("ir,jr,kr->ijk", dict(i=7, j=5, k=6, r=3), (1.0, 1.0)),
+    ("wr,dr,hr,irk,jrk->wdhij", dict(w=5, d=3, h=4, i=6, j=5, r=3, k=2), (1.0, 0.0)),
+    ("ir,jr,ak,kr,tr->ijat", dict(i=7, j=6, a=3, t=4, r=3, k=2), (0.7, 0.3)),
+    ("ij,jk,ik->ijk", dict(i=5, j=4, k=3), (1.0, -1.0))])
+def test_slab_sweep_equals_sweep(model_str, sizes, ab):
+    """The slab-by-slab evaluation (for tensors too large to reconstruct at
+    once) gives the same sweep and loss as the whole-tensor one."""
+    g = np.random.default_rng(9)
+    f = [g.gamma(1.0, 1.0, size=s) for s in O.factor_shapes(model_str, sizes)]
+    Y = g.gamma(2.0, 1.0, size=O.reconstruct(model_str, f).shape)
+    M = (g.random(Y.shape) > 0.2).astype(np.uint8)
+    ref = O.sweep(model_str, f, Y, M, *ab, 1e-10)
+    for n_slabs in (1, 3, sizes[model_str.split("->")[1][0]]):
+        got = O.sweep_slabs(model_str, f, Y, M, *ab, 1e-10, n_slabs)
+        for a, b in zip(got, ref):
+            np.testing.assert_allclose(a, b, rtol=1e-12)
+        assert abs(O.loss_slabs(model_str, f, Y, M, *ab, n_slabs) - O.loss(model_str, f, Y, M, *ab)) <= \
+            1e-12 * O.loss(model_str, f, Y, M, *ab)
