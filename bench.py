@@ -34,11 +34,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--beta", type=float, default=1.0)
-    ap.add_argument("--workload", choices=("cp", "batched", "nmf", "tucker", "tt", "uber", "uber400", "icews"),
+    ap.add_argument("--workload", choices=("cp", "batched", "nmf", "tucker", "tt", "uber", "uber400", "icews",
+                                           "manybody"),
                     default="cp",
                     help="cp: the CP 256^3 headline; batched: 96 CP4 problems x 8 restarts; nmf: 200x150 R=8 KL; "
                          "tucker / tt: the Tucker IS and tensor-train workloads; uber / uber400 / icews: "
-                         "the paper's custom strings at its data shapes (synthetic counts)")
+                         "the paper's custom strings at its data shapes (synthetic counts); manybody: "
+                         "'ij,jk,ik->ijk' at 256^3 (the direct lowering)")
     ap.add_argument("--n", type=int, default=256, help="mode size")
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--prec", choices=("fp32", "bf16", "fp16"), default="fp32",
@@ -299,7 +301,10 @@ def bench_single(args):
     from paper_2602_02759_amd import datagen
     from paper_2602_02759_amd.nnef import Plan
     p = {"nmf": datagen.nmf_kl, "tucker": datagen.tucker3, "tt": datagen.tt4, "uber": datagen.uber_problem,
-         "uber400": lambda: datagen.uber_problem(mesh=400), "icews": datagen.icews_problem}[args.workload]()
+         "uber400": lambda: datagen.uber_problem(mesh=400), "icews": datagen.icews_problem,
+         "manybody": lambda: datagen.poisson_problem("manybody", "ij,jk,ik->ijk", dict(i=256, j=256, k=256),
+                                                     1.0, 0.0, seed=83, truth_shape=1.0, missing=0.1,
+                                                     n_sweeps=100)}[args.workload]()
     Y = torch.from_numpy(p.Y).cuda()
     M = torch.from_numpy(p.M).cuda() if p.M is not None else None
     res = {}

@@ -21,7 +21,7 @@ def test_workload_choices():
     bench = importlib.import_module("bench")
     old = sys.argv
     try:
-        for w in ("cp", "batched", "nmf", "tucker", "tt", "uber", "uber400", "icews"):
+        for w in ("cp", "batched", "nmf", "tucker", "tt", "uber", "uber400", "icews", "manybody"):
             sys.argv = ["bench.py", "--workload", w]
             assert bench.parse().workload == w
     finally:
