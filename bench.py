@@ -43,7 +43,7 @@ def parse():
                          "'ij,jk,ik->ijk' at 256^3 (the direct lowering)")
     ap.add_argument("--n", type=int, default=256, help="mode size")
     ap.add_argument("--rank", type=int, default=32)
-    ap.add_argument("--prec", choices=("fp32", "bf16", "fp16"), default="fp32",
+    ap.add_argument("--prec", choices=("fp32", "bf16", "fp16", "bf16_all", "fp16_all"), default="fp32",
                     help="input precision of the N/D contractions")
     ap.add_argument("--cpu-sweeps", type=int, default=3,
                     help="oracle sweeps timed for the CPU baseline (0 disables)")
@@ -482,6 +482,7 @@ def main():
         thr = target * (1 + 1e-4)
         init = [torch.from_numpy(np.maximum(t, 1e-10)).to(dev) for t in p.init]
         plan16 = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, prec="bf16")
+        plan16a = Plan(p.model_str, p.mode_sizes, p.ranks, p.alpha, p.beta, prec="bf16_all")
         run_to_target([("fp32", plain(plan))], Y, M, init, thr, 10, 60)  # warm-up
         arms = {"plain_fp32": [("fp32", plain(plan))],
                 "bf16": [("bf16", plain(plan16)), ("fp32", plain(plan))]}
@@ -492,8 +493,16 @@ def main():
             acc32 = torch.zeros(1, dtype=torch.int32, device=dev)
             arms["bf16_learned"] = [("bf16", with_proposals(plan16, mlp, PROPOSE_EVERY, acc16)),
                                     ("fp32", with_proposals(plan, mlp, PROPOSE_EVERY, acc32))]
+            # BF16 reconstruction inputs as well in the passes without a loss
+            arms["bf16_all_learned"] = [("bf16_all", with_proposals(plan16a, mlp, PROPOSE_EVERY, acc16)),
+                                        ("fp32", with_proposals(plan, mlp, PROPOSE_EVERY, acc32))]
         res = {k: run_to_target(v, Y, M, init, thr, 10, 1000) for k, v in arms.items()}
         if info is not None:
+            # the counters accumulate over both learned arms: the bf16_learned count is taken
+            # by running it again alone
+            acc16.zero_()
+            acc32.zero_()
+            run_to_target(arms["bf16_learned"], Y, M, init, thr, 10, 1000)
             res["bf16_learned"]["proposals_accepted"] = int(acc16.item() + acc32.item())
             res["bf16_learned"]["propose_every"] = PROPOSE_EVERY
             acc16.zero_()
@@ -525,7 +534,7 @@ def main():
         # trajectory parity in the bench line: the GPU loss after 200 sweeps from
         # the seeded init against L_star (FP32 and BF16 contractions)
         final = {}
-        for name, pl in (("fp32", plan), ("bf16", plan16)):
+        for name, pl in (("fp32", plan), ("bf16", plan16), ("bf16_all", plan16a)):
             ff = [t.clone() for t in init]
             pl.step(Y, M, ff, n_sweeps=200)
             lg = pl.loss(Y, M, ff)

@@ -66,7 +66,12 @@ typedef enum {
  * (see nnef_plan), the reconstruction Yhat, the weights, the ratio N/D, the
  * power and the update, and the loss terms are float32; loss sums are
  * float64.  nnef_plan_describe reports the precision chosen for every block. */
-typedef enum { NNEF_FP32 = 0, NNEF_BF16 = 1, NNEF_FP16 = 2 } nnef_prec;
+/* NNEF_BF16_ALL / NNEF_FP16_ALL also round the inputs of the reconstruction
+ * Yhat to BF16 / FP16 (FP32 accumulation) in the passes that compute no loss;
+ * the passes that do (the first block of a sweep when a loss trace is
+ * requested, nnef_loss, the accept test) keep an FP32 reconstruction, so every
+ * reported loss has FP32 terms. */
+typedef enum { NNEF_FP32 = 0, NNEF_BF16 = 1, NNEF_FP16 = 2, NNEF_BF16_ALL = 3, NNEF_FP16_ALL = 4 } nnef_prec;
 
 /* Likelihood family.  NNEF_AB: the (alpha, beta)-divergence (App. B), with
  * the alpha, beta passed to nnef_plan.  The other decomposable likelihoods of

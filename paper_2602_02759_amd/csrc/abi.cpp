@@ -132,6 +132,17 @@ static nnef_status upload_table(nnef_plan_s* p, const std::vector<uint32_t>& t, 
   return NNEF_OK;
 }
 
+// Contraction precision as nnef_plan_describe states it (batched plans keep
+// an FP32 reconstruction).
+static const char* prec_name(int prec, bool batched) {
+  switch (prec) {
+    case NNEF_BF16: return " contract=bf16";
+    case NNEF_FP16: return " contract=fp16";
+    case NNEF_BF16_ALL: return batched ? " contract=bf16" : " contract=bf16 recon=bf16";
+    default: return batched ? " contract=fp16" : " contract=fp16 recon=fp16";
+  }
+}
+
 // Plan set-up shared by nnef_plan and the batched plan.  with_pack: allocate
 // the buffer that holds the mask-packed data; target_wg: workgroups per pass.
 static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes, int n_modes,
@@ -148,9 +159,9 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
       free_plan(p);
       return fail(NNEF_E_ARG, "eps must be a positive finite number");
     }
-    if (p->opt.prec != NNEF_FP32 && p->opt.prec != NNEF_BF16 && p->opt.prec != NNEF_FP16) {
+    if (p->opt.prec < NNEF_FP32 || p->opt.prec > NNEF_FP16_ALL) {
       free_plan(p);
-      return fail(NNEF_E_ARG, "prec must be NNEF_FP32, NNEF_BF16 or NNEF_FP16");
+      return fail(NNEF_E_ARG, "prec must be one of NNEF_FP32, NNEF_BF16, NNEF_FP16, NNEF_BF16_ALL, NNEF_FP16_ALL");
     }
     if (p->opt.family < NNEF_AB || p->opt.family > NNEF_JS) {
       free_plan(p);
@@ -243,7 +254,7 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
       // batched plans (direct_only) contract in FP32 at widths 16 and 64
       const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!direct_only || bp.KP == 32);
       p->description += describe_block(m, bp) +
-                        (lp ? (p->opt.prec == NNEF_BF16 ? " contract=bf16" : " contract=fp16") : " contract=fp32") +
+                        (lp ? prec_name(p->opt.prec, direct_only) : " contract=fp32") +
                         "\n";
     }
     *out = p;
@@ -327,7 +338,7 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
     // batched plans (direct_only) contract in FP32 at widths 16 and 64
       const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!direct_only || bp.KP == 32);
     p->description += describe_block(m, bp) +
-                      (lp ? (p->opt.prec == NNEF_BF16 ? " contract=bf16" : " contract=fp16") : " contract=fp32") + "\n";
+                      (lp ? prec_name(p->opt.prec, direct_only) : " contract=fp32") + "\n";
   }
   if (hipDeviceSynchronize() != hipSuccess) {
     free_plan(p);
@@ -1202,7 +1213,8 @@ static nnef_status batch_tables(nnef_batch_s* b, const float* const* Y, const ui
             const int run = run0 + r;
             float* const* fr = factors + b->run_fac[run];
             FusedArgs a = fused_args(q, bp, Yd, msk, fr);
-            if (bp.KP != 32) a.prec = 0;  // batched passes of widths 16 and 64 contract in FP32
+            // batched passes: widths 16 and 64 contract in FP32, the reconstruction stays FP32
+            a.prec = bp.KP != 32 ? 0 : a.prec > 2 ? a.prec - 2 : a.prec;
             a.partN = b->partN[run];
             a.partD = b->partD[run];
             a.loss_part = mode ? b->lpart[run] : nullptr;

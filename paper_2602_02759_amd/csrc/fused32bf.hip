@@ -1,11 +1,13 @@
 // Fused-pass instantiations for contraction width 32 with BF16 contraction
-// inputs (passes with contractions only; FP16 inputs are in fused32h.hip).
+// inputs: the numerator and denominator (prec 1) or the reconstruction as
+// well (prec 3, passes without a loss); FP16 inputs are in fused32h.hip.
 #include "fused_x32.hpp"
 
 namespace nnef {
 int launch_fused_kp32_fp16(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s);
 int launch_fused_kp32_prec(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
-  if (a.prec == 2) return launch_fused_kp32_fp16(a, wk, vecq, mode, s);
+  if (a.prec == 2 || a.prec == 4) return launch_fused_kp32_fp16(a, wk, vecq, mode, s);
+  if (a.prec == 3) return launch_x32<1, 3>(a, wk, vecq, mode, s);
   return launch_x32<1, 1>(a, wk, vecq, mode, s);
 }
 }  // namespace nnef

@@ -1,8 +1,11 @@
-// Fused-pass instantiations for contraction width 32 with FP16 contraction inputs.
+// Fused-pass instantiations for contraction width 32 with FP16 contraction
+// inputs: the numerator and denominator (prec 2) or the reconstruction as
+// well (prec 4, passes without a loss).
 #include "fused_x32.hpp"
 
 namespace nnef {
 int launch_fused_kp32_fp16(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s) {
+  if (a.prec == 4) return launch_x32<1, 4>(a, wk, vecq, mode, s);
   return launch_x32<1, 2>(a, wk, vecq, mode, s);
 }
 }  // namespace nnef

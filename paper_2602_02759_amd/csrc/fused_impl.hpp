@@ -333,14 +333,18 @@ __device__ __forceinline__ void store_partial(const f4 (&acc)[Tile<KP>::PT][Tile
 
 // One workgroup's tile: braw is the workgroup index within the problem's
 // grid (before the XCD remap), slot its loss-partial index.
-// PREC: input precision of the numerator/denominator contractions (0 = FP32
-// on 16x16x4 f32 MFMA; 1 = BF16, 2 = FP16 on one 16x16x16 MFMA per kappa tile,
-// FP32 accumulation); the reconstruction is always FP32.
+// PREC: input precision of the contractions (0 = FP32 on 16x16x4 f32 MFMA;
+// 1 = BF16, 2 = FP16 numerator/denominator on one 16x16x16 MFMA per kappa tile,
+// FP32 accumulation; 3 = BF16, 4 = FP16 for the reconstruction as well, one
+// 16x16x16 MFMA per subtile, in the passes without a loss).
 template <int KP, int WK, bool VECQ, int MODE, bool FULL, int PREC>
 __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, int slot) {
   using T = Tile<KP>;
   constexpr int PT = T::PT, ROWS = T::ROWS, KS = T::KS, KT = T::KT, RST = T::RST;
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
+  constexpr int LP = PREC > 2 ? PREC - 2 : PREC;
+  constexpr bool LPREC = PREC > 2 && KS == 4;  // reduced-precision reconstruction (width 16)
+  static_assert(PREC <= 2 || !LOSS, "a loss pass keeps an FP32 reconstruction");
   __shared__ f4 red4[ND ? 3 * ROWS * RST / 4 : 1];
   __shared__ double lred[8];
   float* red = reinterpret_cast<float*>(red4);
@@ -537,8 +541,15 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
   // another (scheduling hints below keep that interleave).
   auto recon = [&](int t, const Cols& cl) {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (LPREC) {
+      // lane (g, c) holds kappa 4g .. 4g+3 of its row and column: the K = 16 form
+      const f4 lu = {Lu[t][0], Lu[t][1], Lu[t][2], Lu[t][3]};
+      const float ra[4] = {cl.Ra[0], cl.Ra[1], cl.Ra[2], cl.Ra[3]};
+      acc = mfma4_lp<LP>(ra, lu, acc);
+    } else {
 #pragma unroll
-    for (int s2 = 0; s2 < KS; ++s2) acc = mfma4(cl.Ra[s2], Lu[t][s2], acc);
+      for (int s2 = 0; s2 < KS; ++s2) acc = mfma4(cl.Ra[s2], Lu[t][s2], acc);
+    }
     return acc;
   };
   auto weights = [&](int t, const YM& ym, const f4& yh, f4& wa, f4& wb) {
@@ -583,10 +594,10 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
         // the K = 16 form sums the step's 16 columns q = 4g + r in one
         // instruction: lane (g, c) supplies exactly its four r values
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) tN[t][kt] = mfma4_lp<PREC>(cl.Rb[kt], wa, tN[t][kt]);
+        for (int kt = 0; kt < KT; ++kt) tN[t][kt] = mfma4_lp<LP>(cl.Rb[kt], wa, tN[t][kt]);
         if (!a.no_d) {
 #pragma unroll
-          for (int kt = 0; kt < KT; ++kt) tD[t][kt] = mfma4_lp<PREC>(cl.Rb[kt], wb, tD[t][kt]);
+          for (int kt = 0; kt < KT; ++kt) tD[t][kt] = mfma4_lp<LP>(cl.Rb[kt], wb, tD[t][kt]);
         }
       }
     }
@@ -603,10 +614,10 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
 #if NNEF_SCHED
     // MFMA/VALU interleave: R(0); then per subtile its successor's R (KS
     // MFMAs) or its own ND (8 KT MFMAs) alternating with the weight VALU.
-    __builtin_amdgcn_sched_group_barrier(0x008, KS, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, LPREC ? 1 : KS, 0);
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
-      const int nm = (t + 1 < PT ? KS : 0) + (ND ? (PREC == 0 ? 8 : 2) * KT : 0);
+      const int nm = (t + 1 < PT ? (LPREC ? 1 : KS) : 0) + (ND ? (PREC == 0 ? 8 : 2) * KT : 0);
 #pragma unroll
       for (int j = 0; j < nm; ++j) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -730,11 +741,14 @@ int launch_fused_t(const FusedArgs& a, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-// PREC != 0 is instantiated for the passes with contractions only (modes 0, 1)
+// PREC != 0 is instantiated for the passes with contractions only (modes 0,
+// 1); with a reduced-precision reconstruction (PREC > 2) the pass that also
+// computes the loss keeps it FP32 (PREC - 2)
 template <int KP, int WK, bool VECQ, int PREC>
 int launch_fused_m(const FusedArgs& a, int mode, hipStream_t s) {
   if constexpr (PREC != 0) {
-    return mode == 0 ? launch_fused_t<KP, WK, VECQ, 0, PREC>(a, s) : launch_fused_t<KP, WK, VECQ, 1, PREC>(a, s);
+    constexpr int P1 = PREC > 2 ? PREC - 2 : PREC;
+    return mode == 0 ? launch_fused_t<KP, WK, VECQ, 0, PREC>(a, s) : launch_fused_t<KP, WK, VECQ, 1, P1>(a, s);
   } else {
     switch (mode) {
       case 0: return launch_fused_t<KP, WK, VECQ, 0, 0>(a, s);

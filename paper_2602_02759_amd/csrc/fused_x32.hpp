@@ -53,14 +53,17 @@ __device__ __forceinline__ f16v mfma_lp(const float* av, const float* bv, const 
   }
 }
 
-// PREC: input precision of the numerator/denominator contractions
-// (0 = FP32, 1 = BF16, 2 = FP16); the reconstruction is always FP32.
+// PREC: input precision of the contractions: 0 = FP32; 1 = BF16, 2 = FP16
+// for the numerator and denominator; 3 = BF16, 4 = FP16 for the
+// reconstruction as well (instantiated for the passes without a loss only).
 // One workgroup's tile: braw is the workgroup index within the problem's
 // grid (before the XCD remap), slot its loss-partial index.
 template <int NT, int WK, bool VECQ, int MODE, bool FULL, int PREC>
 __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int slot) {
   constexpr int KP = 32 * NT, ROWS = 32, RST = KP + 4;
   constexpr bool LOSS = MODE >= 1, ND = MODE <= 1;
+  constexpr int LP = PREC > 2 ? PREC - 2 : PREC;  // MFMA input type of the reduced-precision forms
+  static_assert(PREC <= 2 || !LOSS, "a loss pass keeps an FP32 reconstruction");
   // Y ring for the direct-to-LDS prefetch of full tiles: kStages stages of 4 KB
   // per wave; after the main loop the same memory holds the partial reduction.
   constexpr int kStages = 4;
@@ -288,10 +291,19 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
 
   auto compute = [&](const YM& ym, const Cols& cl) {
     f16v yh = {};
+    if constexpr (PREC > 2) {
+      // K = 16 form: MFMA m takes the lane's kappa values 8m .. 8m+7 of each tile
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+      for (int t = 0; t < NT; ++t) {
+        yh = mfma_lp<LP>(cl.Ra[t], Lu[t], yh);
+        yh = mfma_lp<LP>(cl.Ra[t] + 8, Lu[t] + 8, yh);
+      }
+    } else {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) yh = mfma32(cl.Ra[t][s], Lu[t][s], yh);
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) yh = mfma32(cl.Ra[t][s], Lu[t][s], yh);
+    }
     f16v wa, wb;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -337,11 +349,11 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
             wav[v] = wa[v];
             wbv[v] = wb[v];
           }
-          accN[t] = mfma_lp<PREC>(rb, wav, accN[t]);
-          accN[t] = mfma_lp<PREC>(rb + 8, wav + 8, accN[t]);
+          accN[t] = mfma_lp<LP>(rb, wav, accN[t]);
+          accN[t] = mfma_lp<LP>(rb + 8, wav + 8, accN[t]);
           if (!a.no_d) {
-            accD[t] = mfma_lp<PREC>(rb, wbv, accD[t]);
-            accD[t] = mfma_lp<PREC>(rb + 8, wbv + 8, accD[t]);
+            accD[t] = mfma_lp<LP>(rb, wbv, accD[t]);
+            accD[t] = mfma_lp<LP>(rb + 8, wbv + 8, accD[t]);
           }
         }
       }
@@ -568,11 +580,14 @@ int launch_x32_p(const FusedArgs& a, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-// PREC != 0 is instantiated for the passes with contractions only (modes 0, 1)
+// PREC != 0 is instantiated for the passes with contractions only (modes 0,
+// 1); with a reduced-precision reconstruction (PREC > 2) the pass that also
+// computes the loss keeps it FP32 (PREC - 2)
 template <int NT, int WK, bool VECQ, int PREC>
 int launch_x32_m(const FusedArgs& a, int mode, hipStream_t s) {
   if constexpr (PREC != 0) {
-    return mode == 0 ? launch_x32_p<NT, WK, VECQ, 0, PREC>(a, s) : launch_x32_p<NT, WK, VECQ, 1, PREC>(a, s);
+    constexpr int P1 = PREC > 2 ? PREC - 2 : PREC;
+    return mode == 0 ? launch_x32_p<NT, WK, VECQ, 0, PREC>(a, s) : launch_x32_p<NT, WK, VECQ, 1, P1>(a, s);
   } else {
     switch (mode) {
       case 0: return launch_x32_p<NT, WK, VECQ, 0, 0>(a, s);

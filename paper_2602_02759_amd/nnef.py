@@ -20,7 +20,7 @@ _lib = None
 
 STATUS = {0: "NNEF_OK", 1: "NNEF_E_PARSE", 2: "NNEF_E_SHAPE", 3: "NNEF_E_LOSS_UNSUPPORTED",
           4: "NNEF_E_ARG", 5: "NNEF_E_DEVICE", 6: "NNEF_E_NOMEM", 7: "NNEF_E_UNSUPPORTED"}
-PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_all": 3, "fp16_all": 4}
 FAMILY = {"ab": 0, "negbin": 1, "binomial": 2, "js": 3}
 
 

@@ -85,4 +85,8 @@ def test_null_arguments(lib):
     assert st == STATUS["E_ARG"]
     assert lib.nnef_step(None, None, None, None, 1, None, None) == STATUS["E_ARG"]
     lib.nnef_plan_destroy(None)  # accepted, no effect
-    assert nnef.PREC == {"fp32": 0, "bf16": 1, "fp16": 2}
+    # the binding's precision names follow the header's nnef_prec enum
+    text = open(HEADER).read()
+    body = re.search(r"typedef enum \{([^}]*)\} nnef_prec;", text).group(1)
+    enum = {k.strip(): int(v) for k, v in re.findall(r"NNEF_(\w+)\s*=\s*(\d+)", body)}
+    assert {k.lower(): v for k, v in enum.items()} == nnef.PREC

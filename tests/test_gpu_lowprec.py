@@ -32,14 +32,15 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16_all", "fp16_all"])
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_lowprec_step(prec, name):
     p = CASES[name]()
     plan = _plan(p, prec)
     desc = plan.describe()
     print(desc, flush=True)
-    assert f"contract={prec}" in desc
+    base = prec.split("_")[0]
+    assert f"contract={base}" in desc and (f"recon={base}" in desc) == prec.endswith("_all")
     s0 = clamp_init(p)
     g1 = gpu_sweeps(plan, p, s0, 1)
     worst = assert_step_parity(g1, oracle_sweep(p, s0), 1e-2, f"{name} {prec}")
@@ -84,3 +85,19 @@ def test_bf16_trajectory_final_loss_other_widths(name, n_sweeps):
     lr = O.loss(p.model_str, ref, p.Y, p.M, p.alpha, p.beta)
     print(f"{name} bf16 {n_sweeps}-sweep loss {lg:.8e} oracle {lr:.8e} rel {(lg - lr) / lr:.2e}")
     assert abs(lg - lr) <= 1e-4 * lr
+
+
+@pytest.mark.parametrize("prec", ["bf16_all", "fp16_all"])
+def test_reduced_precision_reconstruction_keeps_fp32_losses(prec):
+    """With the reconstruction's inputs rounded as well, the loss trace (taken in
+    the first pass of each sweep, which keeps an FP32 reconstruction) still
+    matches the oracle at 1e-5 for the state it belongs to."""
+    p = CASES["cp3_small_kl"]()
+    plan = _plan(p, prec)
+    s0 = clamp_init(p)
+    g, tr = gpu_sweeps(plan, p, s0, 3, trace=True)
+    ref = O.loss(p.model_str, [s.astype(np.float64) for s in s0], p.Y, p.M, p.alpha, p.beta)
+    assert abs(tr[0] - ref) <= 1e-5 * ref
+    g2 = gpu_sweeps(plan, p, g, 1, trace=True)[1]
+    ref2 = O.loss(p.model_str, [s.astype(np.float64) for s in g], p.Y, p.M, p.alpha, p.beta)
+    assert abs(g2[0] - ref2) <= 1e-5 * ref2

@@ -52,7 +52,7 @@ def _run(p, prec):
     return states, tr.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_all"])
 @pytest.mark.parametrize("ab", [(1.0, 1.0), (0.5, 1.0)])
 def test_cp3_full_trajectory(ab, prec):
     print(f"[trajectory] CP 256^3 R=32 ab={ab} {prec}", flush=True)
