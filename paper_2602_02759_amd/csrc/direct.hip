@@ -129,9 +129,19 @@ __global__ __launch_bounds__(256) void direct_pass(DirectArgs a) {
   }
   if constexpr (ND) {
     // thread tid = ((ql * rows_per_wg + rl) * G + gi) holds r = gi + G i of its
-    // row; every output (row, r) sums the column lanes in lane order
+    // row.  The column lanes of a row that share a wave are summed first by a
+    // butterfly over the lane bits at and above span = rows_per_wg * G (all of
+    // them end with the same sum); the lanes below span then hold one value per
+    // group of 64 / span column lanes, and every output (row, r) sums those
+    // groups in lane order.
     const int nout = a.rows_per_wg * K;
-    auto reduce = [&](const float (&acc)[KPT], float* dst) {
+    const int span = a.rows_per_wg * G;
+    const int grp = span < 64 ? 64 / span : 1;
+    auto reduce = [&](float (&acc)[KPT], float* dst) {
+      for (int o = span; o < 64; o <<= 1) {
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) acc[i] += __shfl_xor(acc[i], o, 64);
+      }
 #pragma unroll
       for (int i = 0; i < KPT; ++i) red[tid * KPT + i] = acc[i];
       __syncthreads();
@@ -139,7 +149,7 @@ __global__ __launch_bounds__(256) void direct_pass(DirectArgs a) {
         const int rr = o / K, r = o - rr * K;
         const int g2 = r & (G - 1), i2 = r / G;
         float v = 0.f;
-        for (int l = 0; l < a.qlanes; ++l) v += red[((l * a.rows_per_wg + rr) * G + g2) * KPT + i2];
+        for (int l = 0; l < a.qlanes; l += grp) v += red[((l * a.rows_per_wg + rr) * G + g2) * KPT + i2];
         const int pp = panel * a.rows_per_wg + rr;
         if (pp < a.nP) dst[((size_t)chunk * a.nP + pp) * K + r] = v;
       }

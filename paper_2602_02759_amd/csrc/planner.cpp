@@ -612,8 +612,8 @@ Status lower_direct(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>
   while (G * kDirectKPT < K) G *= 2;
   b.G = G;
   const int eg = 256 / G;
-  int ql = 1;
-  while (ql * 2 <= eg && ql * 2 <= b.nQ) ql *= 2;
+  int ql = 1;  // column lanes per row: about eight entries per thread when the row is long enough
+  while (ql * 2 <= eg && ql * 2 <= std::max<int64_t>(1, b.nQ / 8)) ql *= 2;
   b.qlanes = ql;
   b.rows_per_wg = eg / ql;
   const int64_t panels = (b.nP + b.rows_per_wg - 1) / b.rows_per_wg;
