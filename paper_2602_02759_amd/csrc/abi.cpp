@@ -379,38 +379,73 @@ static const float* tensor_ptr(const nnef_plan_s* p, const BlockPlan& bp, const 
   }
 }
 
+static EinsumArgs einsum_args(const nnef_plan_s* p, const BlockPlan& bp, const Step& st,
+                              const float* const* factors) {
+  const Model& m = p->m;
+  EinsumArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n_in = (int)st.in.size();
+  a.n_out = (int)st.out.subs.size();
+  a.n_sum = (int)st.sum.size();
+  a.n_out_total = 1;
+  for (int d = 0; d < a.n_out; ++d) {
+    const char c = st.out.subs[d];
+    a.out_size[d] = m.size[(unsigned char)c];
+    a.out_stride[d] = st.out.strides[d];
+    a.n_out_total *= a.out_size[d];
+  }
+  for (int d = 0; d < a.n_sum; ++d) a.sum_size[d] = m.size[(unsigned char)st.sum[d]];
+  for (int i = 0; i < a.n_in; ++i) {
+    const TensorRef& t = st.in[i];
+    a.in[i] = tensor_ptr(p, bp, t, factors);
+    for (int d = 0; d < a.n_out; ++d) {
+      const size_t pos = t.subs.find(st.out.subs[d]);
+      a.in_out_stride[i][d] = pos == std::string::npos ? 0 : t.strides[pos];
+    }
+    for (int d = 0; d < a.n_sum; ++d) {
+      const size_t pos = t.subs.find(st.sum[d]);
+      a.in_sum_stride[i][d] = pos == std::string::npos ? 0 : t.strides[pos];
+    }
+  }
+  a.out = const_cast<float*>(tensor_ptr(p, bp, st.out, factors));
+  return a;
+}
+
 static int run_program(const nnef_plan_s* p, const BlockPlan& bp, const std::vector<Step>& prog,
                        const float* const* factors, hipStream_t s) {
-  const Model& m = p->m;
   for (const Step& st : prog) {
-    EinsumArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.n_in = (int)st.in.size();
-    a.n_out = (int)st.out.subs.size();
-    a.n_sum = (int)st.sum.size();
-    a.n_out_total = 1;
-    for (int d = 0; d < a.n_out; ++d) {
-      const char c = st.out.subs[d];
-      a.out_size[d] = m.size[(unsigned char)c];
-      a.out_stride[d] = st.out.strides[d];
-      a.n_out_total *= a.out_size[d];
-    }
-    for (int d = 0; d < a.n_sum; ++d) a.sum_size[d] = m.size[(unsigned char)st.sum[d]];
-    for (int i = 0; i < a.n_in; ++i) {
-      const TensorRef& t = st.in[i];
-      a.in[i] = tensor_ptr(p, bp, t, factors);
-      for (int d = 0; d < a.n_out; ++d) {
-        const size_t pos = t.subs.find(st.out.subs[d]);
-        a.in_out_stride[i][d] = pos == std::string::npos ? 0 : t.strides[pos];
-      }
-      for (int d = 0; d < a.n_sum; ++d) {
-        const size_t pos = t.subs.find(st.sum[d]);
-        a.in_sum_stride[i][d] = pos == std::string::npos ? 0 : t.strides[pos];
-      }
-    }
-    a.out = const_cast<float*>(tensor_ptr(p, bp, st.out, factors));
-    const int e = launch_einsum(a, s);
+    const int e = launch_einsum(einsum_args(p, bp, st, factors), s);
     if (e) return e;
+  }
+  return 0;
+}
+
+// Two programs evaluated step by step together: the numerator and denominator
+// chains of a block, built alike from N_L and D_L, share each launch.
+static int run_program_pair(const nnef_plan_s* p, const BlockPlan& bp, const std::vector<Step>& pa,
+                            const std::vector<Step>& pb, const float* const* factors, hipStream_t s) {
+  if (pa.size() != pb.size()) {
+    const int e = run_program(p, bp, pa, factors, s);
+    return e ? e : run_program(p, bp, pb, factors, s);
+  }
+  for (size_t i = 0; i < pa.size(); ++i) {
+    EinsumArgs a = einsum_args(p, bp, pa[i], factors);
+    EinsumArgs b = einsum_args(p, bp, pb[i], factors);
+    bool same = a.n_in == b.n_in && a.n_out == b.n_out && a.n_sum == b.n_sum && a.n_out_total == b.n_out_total;
+    for (int d = 0; same && d < a.n_out; ++d) {
+      same = a.out_size[d] == b.out_size[d] && a.out_stride[d] == b.out_stride[d];
+      for (int j = 0; j < a.n_in; ++j) same = same && a.in_out_stride[j][d] == b.in_out_stride[j][d];
+    }
+    for (int d = 0; same && d < a.n_sum; ++d) {
+      same = a.sum_size[d] == b.sum_size[d];
+      for (int j = 0; j < a.n_in; ++j) same = same && a.in_sum_stride[j][d] == b.in_sum_stride[j][d];
+    }
+    const int e = same ? launch_einsum(a, s, &b) : launch_einsum(a, s);
+    if (e) return e;
+    if (!same) {
+      const int e2 = launch_einsum(b, s);
+      if (e2) return e2;
+    }
   }
   return 0;
 }
@@ -590,8 +625,7 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
     e = launch_update(ua, p->dcol, s);
     if (e) return hip_fail(e, "update launch");
     if (!bp.L_direct) {
-      e = run_program(p, bp, bp.chainN, cf, s);
-      if (!e) e = run_program(p, bp, bp.chainD, cf, s);
+      e = run_program_pair(p, bp, bp.chainN, bp.chainD, cf, s);
       if (e) return hip_fail(e, "chain-back contraction launch");
       ApplyArgs aa;
       aa.theta = factors[l];

@@ -488,6 +488,9 @@ struct GemmArgs {
   const float* X;
   const float* Y;
   float* out;
+  const float* X2;                     // a second problem of the same shape (blockIdx.y = 1)
+  const float* Y2;
+  float* out2;
   GemmGroup gm, gn, gb;
   int64_t M, N, B, K;
   int64_t kx, ky;                      // strides of the summed letter in X and Y
@@ -498,11 +501,13 @@ struct Off3 {
   int64_t x, y, o;
 };
 
-__device__ __forceinline__ Off3 group_offsets(const GemmGroup& g, int64_t idx) {
+__device__ __forceinline__ Off3 group_offsets(const GemmGroup& g, int64_t idx64) {
   Off3 r{0, 0, 0};
+  uint32_t idx = (uint32_t)idx64;  // the host keeps M, N and B below 2^31
   for (int d = g.n - 1; d >= 0; --d) {
-    const int64_t v = idx % g.size[d];
-    idx /= g.size[d];
+    const uint32_t sz = (uint32_t)g.size[d];
+    const int64_t v = (int64_t)(idx % sz);
+    idx /= sz;
     r.x += v * g.sx[d];
     r.y += v * g.sy[d];
     r.o += v * g.so[d];
@@ -510,17 +515,19 @@ __device__ __forceinline__ Off3 group_offsets(const GemmGroup& g, int64_t idx) {
   return r;
 }
 
-// SPLIT: few tiles and a long sum.  The four waves of a workgroup take the
-// same tile and a quarter of k each; wave 0 adds the other waves' sums in wave
-// order (deterministic) and stores the tile.
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void einsum_gemm_kernel(GemmArgs a) {
+// WPT waves share one 32 x 32 tile and split the sum into WPT even shares
+// (WPT = 1: four tiles per 256-thread workgroup, each wave the whole sum);
+// wave 0 adds the other waves' sums in wave order (deterministic) and stores
+// the tile.  Each wave keeps the loads of its next sixteen k in flight while
+// it issues the eight MFMA of the current ones.
+template <int WPT>
+__global__ __launch_bounds__(WPT == 1 ? 256 : 64 * WPT) void einsum_gemm_kernel(GemmArgs a) {
   typedef float f16v __attribute__((ext_vector_type(16)));
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int64_t w = SPLIT ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wv;
+  const int64_t w = WPT == 1 ? (int64_t)blockIdx.x * 4 + wv : (int64_t)blockIdx.x;
   const int64_t n_tiles = a.tiles_m * a.tiles_n * a.B;
-  if (w >= n_tiles) return;  // whole waves (whole workgroups when SPLIT), before any barrier
+  if (w >= n_tiles) return;  // whole waves (whole workgroups when WPT > 1), before any barrier
   const int g = lane >> 5, c = lane & 31;
   const int64_t tn = w % a.tiles_n, tm = (w / a.tiles_n) % a.tiles_m, bb = w / (a.tiles_n * a.tiles_m);
   const int64_t m = tm * 32 + c, n = tn * 32 + c;
@@ -528,47 +535,51 @@ __global__ __launch_bounds__(256) void einsum_gemm_kernel(GemmArgs a) {
   const Off3 ob = group_offsets(a.gb, bb);
   const Off3 om = group_offsets(a.gm, mv ? m : 0);
   const Off3 on = group_offsets(a.gn, nv ? n : 0);
+  const bool second = blockIdx.y != 0;
+  const float* X = second ? a.X2 : a.X;
+  const float* Y = second ? a.Y2 : a.Y;
+  float* out = second ? a.out2 : a.out;
   int64_t kb = 0, ke = a.K;
-  if constexpr (SPLIT) {
-    const int64_t kq = (a.K + 7) / 8 * 2;  // a quarter of the sum, rounded up to an even count
+  if constexpr (WPT > 1) {
+    const int64_t kq = (a.K + 2 * WPT - 1) / (2 * WPT) * 2;  // a share of the sum, rounded up to even
     kb = wv * kq < a.K ? wv * kq : a.K;
     ke = kb + kq < a.K ? kb + kq : a.K;
   }
-  const float* xp = a.X + ob.x + om.x + (kb + g) * a.kx;
-  const float* yp = a.Y + ob.y + on.y + (kb + g) * a.ky;
-  const int64_t kx2 = 2 * a.kx, ky2 = 2 * a.ky;
-  f16v acc = {};
-  int64_t k0 = kb;
-  for (; k0 + 16 <= ke; k0 += 16) {  // eight steps with every load issued first
-    float av[8], bv[8];
+  const float* xp = X + ob.x + om.x + g * a.kx;
+  const float* yp = Y + ob.y + on.y + g * a.ky;
+  const int64_t kx = a.kx, ky = a.ky;
+  auto load = [&](int64_t k0, float (&av)[8], float (&bv)[8]) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      av[j] = mv ? xp[j * kx2] : 0.f;
-      bv[j] = nv ? yp[j * ky2] : 0.f;
+      const int64_t kk = k0 + 2 * j;
+      const bool kv = kk + g < ke;
+      av[j] = (mv && kv) ? xp[kk * kx] : 0.f;
+      bv[j] = (nv && kv) ? yp[kk * ky] : 0.f;
     }
+  };
+  f16v acc = {};
+  float an[8], bn[8];
+  if (kb < ke) load(kb, an, bn);
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    float ac[8], bc[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], acc, 0, 0, 0);
-    xp += 8 * kx2;
-    yp += 8 * ky2;
+    for (int j = 0; j < 8; ++j) {
+      ac[j] = an[j];
+      bc[j] = bn[j];
+    }
+    if (k0 + 16 < ke) load(k0 + 16, an, bn);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[j], bc[j], acc, 0, 0, 0);
   }
-  for (; k0 < ke; k0 += 2) {
-    const bool kv = k0 + g < ke;
-    const float av = (mv && kv) ? xp[0] : 0.f;
-    const float bv = (nv && kv) ? yp[0] : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-    xp += kx2;
-    yp += ky2;
-  }
-  if constexpr (SPLIT) {
-    __shared__ float red[3][16][64];
+  if constexpr (WPT > 1) {
+    __shared__ float red[WPT - 1][16][64];
     if (wv > 0) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) red[wv - 1][v][lane] = acc[v];
     }
     __syncthreads();
     if (wv != 0) return;
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < WPT - 1; ++q)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] += red[q][v][lane];
   }
@@ -581,7 +592,7 @@ __global__ __launch_bounds__(256) void einsum_gemm_kernel(GemmArgs a) {
     const int lo = __shfl((int)(uint32_t)om.o, r, 64);
     const int hi = __shfl((int)(uint32_t)((uint64_t)om.o >> 32), r, 64);
     const int64_t rowo = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-    if (nv && tm * 32 + r < a.M) a.out[base + rowo] = acc[v];
+    if (nv && tm * 32 + r < a.M) out[base + rowo] = acc[v];
   }
 }
 
@@ -592,6 +603,8 @@ bool gemm_args(const EinsumArgs& e, GemmArgs& g) {
   g.X = e.in[0];
   g.Y = e.in[1];
   g.out = e.out;
+  g.X2 = g.Y2 = nullptr;
+  g.out2 = nullptr;
   g.gm.n = g.gn.n = g.gb.n = 0;
   g.M = g.N = g.B = 1;
   for (int d = 0; d < e.n_out; ++d) {
@@ -659,23 +672,44 @@ static EinsumArgs merge_sum_letters(EinsumArgs a) {
   return a;
 }
 
-int launch_einsum(const EinsumArgs& a_in, void* stream) {
+// Two contractions that differ only in their operand and output pointers
+// (the numerator and denominator chains of one block) go out as one launch
+// when they take the matrix-product form; otherwise one after the other.
+int launch_einsum(const EinsumArgs& a_in, void* stream, const EinsumArgs* second) {
   const EinsumArgs a = merge_sum_letters(a_in);
   if (a.n_out_total <= 0) return 0;
   int64_t n_sum = 1;
   for (int d = 0; d < a.n_sum; ++d) n_sum *= a.sum_size[d];
   GemmArgs ga;
-  if (gemm_args(a, ga) && ga.M >= 8 && ga.N >= 8 && ga.M * ga.N * ga.B * ga.K >= (int64_t(1) << 20)) {
+  if (gemm_args(a, ga) && ga.M >= 8 && ga.N >= 8 && ga.M * ga.N * ga.B * ga.K >= (int64_t(1) << 20) &&
+      ga.M < (int64_t(1) << 31) && ga.N < (int64_t(1) << 31) && ga.B < (int64_t(1) << 31)) {
     const int64_t tiles = ga.tiles_m * ga.tiles_n * ga.B;
-    if (tiles < 2048 && ga.K >= 64) {  // too few tiles to fill the chip: four waves per tile
-      hipLaunchKernelGGL(einsum_gemm_kernel<true>, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, ga);
+    const unsigned pairs = second ? 2u : 1u;
+    if (second) {
+      ga.X2 = second->in[0];
+      ga.Y2 = second->in[1];
+      ga.out2 = second->out;
+    }
+    // too few tiles to fill the chip: the waves of a workgroup split the sum
+    if (tiles < 512 && ga.K >= 256) {
+      hipLaunchKernelGGL(einsum_gemm_kernel<8>, dim3((unsigned)tiles, pairs), dim3(512), 0, (hipStream_t)stream,
+                         ga);
+      return (int)hipGetLastError();
+    }
+    if (tiles < 2048 && ga.K >= 64) {
+      hipLaunchKernelGGL(einsum_gemm_kernel<4>, dim3((unsigned)tiles, pairs), dim3(256), 0, (hipStream_t)stream,
+                         ga);
       return (int)hipGetLastError();
     }
     if ((tiles + 3) / 4 < (int64_t(1) << 31)) {
-      hipLaunchKernelGGL(einsum_gemm_kernel<false>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0,
+      hipLaunchKernelGGL(einsum_gemm_kernel<1>, dim3((unsigned)((tiles + 3) / 4), pairs), dim3(256), 0,
                          (hipStream_t)stream, ga);
       return (int)hipGetLastError();
     }
+  }
+  if (second) {
+    const int e = launch_einsum(a_in, stream, nullptr);
+    return e ? e : launch_einsum(*second, stream, nullptr);
   }
   if (n_sum >= 16 && n_sum < (int64_t(1) << 31) && a.n_in >= 1 && a.n_in <= 4) {
     // lanes per output: enough threads to fill the chip, at most 64

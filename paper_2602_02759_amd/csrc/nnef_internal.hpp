@@ -195,7 +195,9 @@ int launch_update(const UpdateArgs& a, float* dcol, void* stream);  // dcol: [K]
 // no_d), then the update over the work items (run, 64-output block).
 int launch_update_batched(const UpdateArgs* args, const int* colsum_runs, int n_colsum,
                           const WorkItem* work, int n_work, int grid, void* stream);
-int launch_einsum(const EinsumArgs& a, void* stream);
+// second (may be null): a contraction of the same shape and strides, other
+// pointers; both are evaluated (in one launch where the form allows)
+int launch_einsum(const EinsumArgs& a, void* stream, const EinsumArgs* second = nullptr);
 int launch_apply(const ApplyArgs& a, void* stream);
 int launch_loss_final(const double* part, int n, double* out, void* stream);
 int launch_zero(float* p, int64_t n, void* stream);

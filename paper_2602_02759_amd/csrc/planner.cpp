@@ -367,7 +367,7 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
         bp2.L_buf = out.id;
         bp2.ldL = KP;
         bp2.L_prog = plan_contraction(m, pops, out, ws2, macs);
-        mat_elems += (double)bp2.nP * KP;
+        mat_elems += (double)bp2.nP * (KP + 2.0 * K);  // L, and N_L, D_L for the chain-back
         // chain-back: N_l = einsum(P-side operands except l, N_L -> ops[l])
         std::vector<TensorRef> cin;
         for (auto& t : pops)
@@ -399,54 +399,101 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
         bp2.DL_buf = (int)ws2.size();
         ws2.push_back(bp2.nP * K);
       }
-      // ---- column side R: product of pieces, or one materialised piece
-      bool kr = !q_empty && !qops.empty() && (int)qops.size() <= kMaxPieces;
-      const char qi_letter = q_empty ? 0 : bp2.Q.back();
-      int n_with_qi = 0;
-      for (auto& t : qops) {
-        std::string ob;
-        for (char c : t.subs)
-          if (m.out.find(c) != std::string::npos) ob.push_back(c);
-        kr &= !ob.empty() && t.subs == ob + kappa;
-        n_with_qi += ob.find(qi_letter) != std::string::npos ? 1 : 0;
-      }
-      kr &= n_with_qi == 1;  // one inner piece, the others indexed by qo only
+      // ---- column side R: a product of pieces.  Column-side operands that
+      // share an observed letter, or a latent letter outside kappa, belong to
+      // one piece (operands with no observed letter join the first piece).  A
+      // piece of one operand laid out as [its observed letters, kappa] is that
+      // factor itself; any other piece is contracted before the pass into a
+      // buffer [its observed letters in Y order, kappa] (when that piece spans
+      // every column letter, this is the whole column side materialised).
       bp2.pieces.clear();
-      if (kr) {
-        for (auto& t : qops) {
-          Piece pc;
-          pc.factor = t.id;
-          pc.ld = (int)K;
-          pc.obs.clear();
-          for (char c : t.subs)
-            if (m.out.find(c) != std::string::npos) pc.obs.push_back(c);
-          pc.nrows = 1;
-          for (char c : pc.obs) pc.nrows *= m.size[(unsigned char)c];
-          bp2.pieces.push_back(pc);
+      std::vector<std::vector<int>> groups;  // indices into qops
+      if (!q_empty && !qops.empty()) {
+        const int nq = (int)qops.size();
+        std::vector<int> root(nq);
+        for (int i = 0; i < nq; ++i) root[i] = i;
+        auto find = [&](int i) {
+          while (root[i] != i) i = root[i] = root[root[i]];
+          return i;
+        };
+        for (int i = 0; i < nq; ++i)
+          for (int j = i + 1; j < nq; ++j)
+            for (char c : qops[i].subs)
+              if (qops[j].subs.find(c) != std::string::npos && !kap.count(c)) root[find(j)] = find(i);
+        std::vector<int> order;  // group roots, first appearance
+        for (int i = 0; i < nq; ++i)
+          if (std::find(order.begin(), order.end(), find(i)) == order.end()) order.push_back(find(i));
+        for (int g : order) {
+          std::vector<int> mem;
+          for (int i = 0; i < nq; ++i)
+            if (find(i) == g) mem.push_back(i);
+          groups.push_back(mem);
         }
-      } else {
+        auto has_obs = [&](const std::vector<int>& mem) {
+          for (int i : mem)
+            for (char c : qops[i].subs)
+              if (m.out.find(c) != std::string::npos) return true;
+          return false;
+        };
+        int first = -1;
+        for (int g = 0; g < (int)groups.size() && first < 0; ++g)
+          if (has_obs(groups[g])) first = g;
+        for (int g = (int)groups.size() - 1; g >= 0 && first >= 0; --g)
+          if (!has_obs(groups[g])) {
+            groups[first].insert(groups[first].end(), groups[g].begin(), groups[g].end());
+            groups.erase(groups.begin() + g);
+            if (g < first) --first;
+          }
+      }
+      if (q_empty) {
         Piece pc;
         pc.factor = -1;
         pc.ld = KP;
         pc.nrows = bp2.nQ;
-        if (q_empty) {
-          pc.ws = (int)ws2.size();  // a single row [1, 0, ...]
-          ws2.push_back(KP);
-          bp2.ones_buf = pc.ws;
-        } else {
-          TensorRef out;
-          out.kind = TK_WS;
-          out.id = (int)ws2.size();
-          out.subs = bp2.Q + kappa;
-          ws2.push_back(bp2.nQ * KP);
-          out.strides = row_major_strides(m, bp2.Q, KP);
-          auto ks = row_major_strides(m, kappa, 1);
-          out.strides.insert(out.strides.end(), ks.begin(), ks.end());
-          pc.ws = out.id;
-          bp2.R_prog = plan_contraction(m, qops, out, ws2, macs);
-          mat_elems += (double)bp2.nQ * KP;
-        }
+        pc.ws = (int)ws2.size();  // a single row [1, 0, ...]
+        ws2.push_back(KP);
+        bp2.ones_buf = pc.ws;
         bp2.pieces.push_back(pc);
+      } else {
+        if (groups.empty() || (int)groups.size() > kMaxPieces) continue;
+        for (auto& mem : groups) {
+          std::set<char> obs_set;
+          std::vector<TensorRef> gops;
+          for (int i : mem) {
+            gops.push_back(qops[i]);
+            for (char c : qops[i].subs)
+              if (m.out.find(c) != std::string::npos) obs_set.insert(c);
+          }
+          Piece pc;
+          pc.nrows = 1;
+          for (char c : obs_set) pc.nrows *= m.size[(unsigned char)c];
+          std::string ob0;
+          for (char c : gops[0].subs)
+            if (m.out.find(c) != std::string::npos) ob0.push_back(c);
+          if (gops.size() == 1 && gops[0].subs == ob0 + kappa) {
+            pc.factor = gops[0].id;
+            pc.ld = (int)K;
+            pc.obs = ob0;
+          } else {
+            const bool whole = obs_set.size() == bp2.Q.size();
+            pc.factor = -1;
+            pc.obs = letters_in_order(m.out, obs_set);
+            pc.ld = whole ? KP : (int)K;
+            TensorRef out;
+            out.kind = TK_WS;
+            out.id = (int)ws2.size();
+            out.subs = pc.obs + kappa;
+            ws2.push_back(pc.nrows * pc.ld);
+            out.strides = row_major_strides(m, pc.obs, pc.ld);
+            auto ks = row_major_strides(m, kappa, 1);
+            out.strides.insert(out.strides.end(), ks.begin(), ks.end());
+            pc.ws = out.id;
+            auto steps = plan_contraction(m, gops, out, ws2, macs);
+            bp2.R_prog.insert(bp2.R_prog.end(), steps.begin(), steps.end());
+            mat_elems += (double)pc.nrows * pc.ld;
+          }
+          bp2.pieces.push_back(pc);
+        }
       }
       {
         std::set<char> seen;
@@ -468,7 +515,7 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
       bp2.outers.clear();
       bp2.inner = 0;
       bp2.in_stride = q_empty ? 0 : 1;
-      if (kr) {
+      if (!q_empty) {
         for (int i = 0; i < (int)bp2.pieces.size(); ++i) {
           const Piece& pc = bp2.pieces[i];
           const size_t pos = pc.obs.find(bp2.qi);
@@ -489,8 +536,11 @@ Status lower_block(const Model& m, int ell, BlockPlan& bp, std::vector<int64_t>&
       const int qstep = KP == 16 ? 16 : 32;
       const double Neff = std::ceil((double)bp2.nP / rows) * rows * (double)bp2.nqo *
                           std::ceil((double)bp2.nqi / qstep) * qstep;
-      const double cost = Neff * 6.0 * KP + 16.0 * macs + 8.0 * mat_elems;
-      if (direct_only && (!bp2.L_direct || !kr)) continue;
+      // a materialised float is written once and read back once: about 8 bytes
+      // of HBM traffic, priced at ~12 MFMA flops per byte (the fused pass's
+      // sustained flop rate over the sustained HBM rate of the side kernels)
+      const double cost = Neff * 6.0 * KP + 16.0 * macs + 96.0 * mat_elems;
+      if (direct_only && (!bp2.L_direct || q_empty || !bp2.R_prog.empty())) continue;
       if (best_cost < 0 || cost < best_cost) {
         best_cost = cost;
         best = bp2;
@@ -728,7 +778,7 @@ bool choose_geometry(const Model& m, BlockPlan& bp, int target_wg) {
 
 std::vector<uint32_t> inner_base_table(const Model& m, const BlockPlan& bp) {
   const Piece& pc = bp.pieces[bp.inner];
-  if (pc.factor < 0) {  // materialised rows: q = qo * nqi + qi
+  if (pc.obs.empty()) {  // the single row of an empty column side
     std::vector<uint32_t> t((size_t)bp.nqo);
     for (int64_t i = 0; i < bp.nqo; ++i) t[(size_t)i] = (uint32_t)(i * bp.nqi);
     return t;
@@ -761,8 +811,10 @@ std::string describe_block(const Model& m, const BlockPlan& bp) {
   if (bp.pieces.size() == 1 && bp.pieces[0].factor < 0) o << "materialised";
   else {
     o << "product(";
-    for (size_t i = 0; i < bp.pieces.size(); ++i)
-      o << (i ? "," : "") << m.ops[bp.pieces[i].factor];
+    for (size_t i = 0; i < bp.pieces.size(); ++i) {
+      const Piece& pc = bp.pieces[i];
+      o << (i ? "," : "") << (pc.factor >= 0 ? m.ops[pc.factor] : "[" + pc.obs + bp.kappa + "]");
+    }
     o << ")";
   }
   o << (bp.L_direct ? "" : " chain-back") << " qo={" << bp.qo << "} qi=" << (bp.qi ? bp.qi : '-')

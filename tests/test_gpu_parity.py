@@ -50,6 +50,9 @@ def _case(name):
     if name == "tucker_odd_sum":  # chain-back sums of odd length >= 64 over few tiles: the four
         # waves of a side-contraction workgroup split the sum, the last part ragged
         return datagen.tucker3(I=97, J=95, K=40, Ra=32, Rb=32, Rc=16, seed=35)
+    if name == "tucker_long_sum":  # a chain-back sum of odd length >= 256 over 64 tiles: eight waves
+        # of a side-contraction workgroup split it, the last share ragged
+        return datagen.tucker3(I=301, J=301, K=64, Ra=32, Rb=32, Rc=16, seed=36)
     if name == "tt_small":
         return datagen.tt4(I=13, J=11, K=9, Lm=7, Ra=3, Rb=4, Rc=5, seed=41)
     if name == "tt_mid":
@@ -75,11 +78,19 @@ def _case(name):
                                        truth_shape=0.5, missing=0.1)
     if name == "icews_tall":  # many rows, few column steps: one row panel per wave (ragged)
         return datagen.poisson_problem("icews_tall", "ir,jr,ak,kr,tr->ijat",
-                                       dict(i=40, j=40, a=10, t=12, r=32, k=4), 1.0, 1.0, seed=68,
+                                       dict(i=60, j=60, a=12, t=6, r=32, k=4), 1.0, 1.0, seed=68,
                                        truth_shape=0.5, missing=0.1)
     if name == "icews_tall_r64":  # width 64 (32x32 tiles, two kappa tiles) with one row panel per wave
         return datagen.poisson_problem("icews_tall_r64", "ir,jr,ak,kr,tr->ijat",
-                                       dict(i=40, j=40, a=10, t=12, r=64, k=4), 1.0, 0.0, seed=82,
+                                       dict(i=60, j=60, a=12, t=6, r=64, k=4), 1.0, 0.0, seed=82,
+                                       truth_shape=0.5, missing=0.1)
+    if name == "icews_grouped":  # column pieces jr and [a, r] = sum_k ak kr (contracted before the pass)
+        return datagen.poisson_problem("icews_grouped", "ir,jr,ak,kr,tr->ijat",
+                                       dict(i=40, j=40, a=16, t=8, r=32, k=4), 1.0, 0.0, seed=83,
+                                       truth_shape=0.5, missing=0.1)
+    if name == "grouped_ija":  # the same grouping with K = 16 (width 16) and ragged rows
+        return datagen.poisson_problem("grouped_ija", "ir,jr,ak,kr->ija",
+                                       dict(i=61, j=48, a=40, r=16, k=4), 0.5, 1.0, seed=84,
                                        truth_shape=0.5, missing=0.1)
     if name == "cp3_full_r64":
         return datagen.cp3(1.0, 1.0, R=64)
@@ -141,7 +152,8 @@ SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_ge
          "tucker_mid", "tt_small", "tt_mid", "cp4_r64", "cp4_r4", "manybody", "uber", "icews", "rkl",
          "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full",
          "lr_tucker", "lr_tucker_w32", "wits", "batched_side_gemm", "manybody_gen", "manybody_rank",
-         "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is", "tucker_odd_sum", "icews_tall_r64"]
+         "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is", "tucker_odd_sum", "icews_tall_r64",
+         "icews_grouped", "grouped_ija", "tucker_long_sum"]
 DIRECT = {"manybody", "manybody_gen", "manybody_rank", "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is"}
 
 

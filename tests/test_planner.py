@@ -33,7 +33,7 @@ def parse(line):
     for key in ("K", "KP", "nP", "nQ", "grid", "chunks", "steps/wave"):
         d[key] = int(re.search(rf"\b{re.escape(key)}=(\d+)", line).group(1))
     d["L"] = re.search(r"\bL=(\w+)", line).group(1)
-    d["R"] = re.search(r"\bR=(materialised|product\([a-zA-Z,]+\))", line).group(1)
+    d["R"] = re.search(r"\bR=(materialised|product\([a-zA-Z,\[\]]+\))", line).group(1)
     d["qi"] = re.search(r"\bqi=([a-zA-Z-])", line).group(1)
     d["contract"] = re.search(r"contract=(\w+)", line).group(1)
     d["vecq"] = " vecq" in line
@@ -110,8 +110,22 @@ def test_tensor_train_and_icews_lowerings():
     assert all(x["KP"] == 16 for x in tt)
     assert sum(x["chain"] for x in tt) >= 2
     ic = dry("ir,jr,ak,kr,tr->ijat", [249, 249, 20, 228], [32, 8], 1.0, 0.0)
-    assert ic[0]["P"] == "iat" and ic[0]["wave_rows"] and ic[0]["steps/wave"] == 8
+    # no block materialises a row side of one row per (i, a, t): the rows of
+    # block ir are (i, a), the columns the product of jr and tr rows
+    assert (ic[0]["P"], ic[0]["R"], ic[0]["qi"]) == ("ia", "product(jr,tr)", "t") and ic[0]["vecq"]
+    assert (ic[1]["P"], ic[1]["R"]) == ("ja", "product(ir,tr)")
+    assert all(x["nP"] <= 4980 for x in ic)
     assert ic[2]["R"] == "product(ir,jr)"
+
+
+def test_grouped_column_pieces():
+    """Column-side operands linked by a latent letter outside kappa form one
+    piece, contracted into a small buffer before the pass: in block ir of
+    'ir,jr,ak,kr->ija' the columns (j, a) are the product of jr rows and rows
+    of [a, r] = sum_k ak kr."""
+    b = dry("ir,jr,ak,kr->ija", [64, 48, 40], [16, 4], 1.0, 0.0)
+    assert (b[0]["P"], b[0]["Q"], b[0]["R"], b[0]["L"]) == ("i", "ja", "product(jr,[ar])", "direct")
+    assert not b[0]["chain"]
 
 
 def test_latent_only_operand_and_shared_letter():
