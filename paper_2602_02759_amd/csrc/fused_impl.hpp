@@ -40,28 +40,35 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 
-// 16x16x16 MFMA with BF16 (PREC 1) or FP16 (PREC 2) inputs rounded from FP32
-// and FP32 accumulation: lane (g, c) supplies A[row c][k 4g + j] = av[j] and
-// B[k 4g + j][col c] = bv[j], j = 0..3.
-template <int PREC>
-__device__ __forceinline__ f4 mfma4_lp(const float (&av)[4], const f4& bv, f4 c) {
-  if constexpr (PREC == 1) {
-    s4v x, y;
+// 16x16x16 MFMA with BF16 (LP 1) or FP16 (LP 2) inputs rounded from FP32 and
+// FP32 accumulation: lane (g, c) supplies A[row c][k 4g + j] and
+// B[k 4g + j][col c], j = 0..3, from four converted values each.  An operand
+// is converted once and may feed several MFMA.
+template <int LP>
+struct Lp4T {
+  typedef s4v v4;  // BF16 bit patterns
+};
+template <>
+struct Lp4T<2> {
+  typedef h4v v4;
+};
+
+template <int LP>
+__device__ __forceinline__ typename Lp4T<LP>::v4 cvt4(float v0, float v1, float v2, float v3) {
+  typename Lp4T<LP>::v4 x;
+  const float v[4] = {v0, v1, v2, v3};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      x[j] = __builtin_bit_cast(short, (__bf16)av[j]);
-      y[j] = __builtin_bit_cast(short, (__bf16)bv[j]);
-    }
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, c, 0, 0, 0);
-  } else {
-    h4v x, y;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      x[j] = (_Float16)av[j];
-      y[j] = (_Float16)bv[j];
-    }
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(x, y, c, 0, 0, 0);
+  for (int j = 0; j < 4; ++j) {
+    if constexpr (LP == 2) x[j] = (_Float16)v[j];
+    else x[j] = __builtin_bit_cast(short, (__bf16)v[j]);
   }
+  return x;
+}
+
+template <int LP>
+__device__ __forceinline__ f4 mfma4v(const typename Lp4T<LP>::v4& a, const typename Lp4T<LP>::v4& b, f4 c) {
+  if constexpr (LP == 2) return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
 // Packed data hold an observed value with its sign bit clear (data are
@@ -279,9 +286,6 @@ struct Tile {
   static constexpr int RST = KP + 4;                            // LDS row stride (floats)
 };
 
-#ifndef NNEF_SCHED
-#define NNEF_SCHED 1
-#endif
 
 // Weight kinds that divide by yhat or raise it to a negative power need
 // yhat >= FLT_MIN (exact arithmetic keeps yhat > 0; FP32 may underflow).
@@ -390,6 +394,7 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
   // by accumulating per-qo partials tN, tD that are scaled by u and added to
   // accN, accD whenever qo changes.  Column-side values stay raw loads.
   float Lu[PT][KS];
+  typename Lp4T<(LP > 0 ? LP : 1)>::v4 LuL[PT];  // Lu converted once per qo (reduced-precision reconstruction)
   f4 uN[KT];  // u at the accumulator rows k = 16 kt + 4g + r
   f4 tN[PT][KT], tD[PT][KT];
   const bool has_outer = a.nouter > 0;
@@ -431,6 +436,10 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
     for (int t = 0; t < PT; ++t)
 #pragma unroll
       for (int s = 0; s < KS; ++s) Lu[t][s] *= uA[s];
+    if constexpr (LPREC) {
+#pragma unroll
+      for (int t = 0; t < PT; ++t) LuL[t] = cvt4<LP>(Lu[t][0], Lu[t][1], Lu[t][2], Lu[t][3]);
+    }
   };
   auto flush = [&]() {
 #pragma unroll
@@ -539,13 +548,13 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
   // p subtiles t, ordered R(0) R(1)|W(0) ND(0)|W(1) ND(1) ... so that the
   // weight arithmetic of one subtile issues in the shadow of the MFMAs of
   // another (scheduling hints below keep that interleave).
+  // reduced-precision column operands of a step, converted once for all subtiles
+  typename Lp4T<(LP > 0 ? LP : 1)>::v4 raL, rbL[KT];
   auto recon = [&](int t, const Cols& cl) {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
     if constexpr (LPREC) {
       // lane (g, c) holds kappa 4g .. 4g+3 of its row and column: the K = 16 form
-      const f4 lu = {Lu[t][0], Lu[t][1], Lu[t][2], Lu[t][3]};
-      const float ra[4] = {cl.Ra[0], cl.Ra[1], cl.Ra[2], cl.Ra[3]};
-      acc = mfma4_lp<LP>(ra, lu, acc);
+      acc = mfma4v<LP>(raL, LuL[t], acc);
     } else {
 #pragma unroll
       for (int s2 = 0; s2 < KS; ++s2) acc = mfma4(cl.Ra[s2], Lu[t][s2], acc);
@@ -593,17 +602,24 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
       } else {
         // the K = 16 form sums the step's 16 columns q = 4g + r in one
         // instruction: lane (g, c) supplies exactly its four r values
+        const auto waL = cvt4<LP>(wa[0], wa[1], wa[2], wa[3]);
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) tN[t][kt] = mfma4_lp<LP>(cl.Rb[kt], wa, tN[t][kt]);
+        for (int kt = 0; kt < KT; ++kt) tN[t][kt] = mfma4v<LP>(rbL[kt], waL, tN[t][kt]);
         if (!a.no_d) {
+          const auto wbL = cvt4<LP>(wb[0], wb[1], wb[2], wb[3]);
 #pragma unroll
-          for (int kt = 0; kt < KT; ++kt) tD[t][kt] = mfma4_lp<LP>(cl.Rb[kt], wb, tD[t][kt]);
+          for (int kt = 0; kt < KT; ++kt) tD[t][kt] = mfma4v<LP>(rbL[kt], wbL, tD[t][kt]);
         }
       }
     }
   };
   auto compute = [&](const YM& ym, const Cols& cl) {
     f4 yh[PT], wa[PT], wb[PT];
+    if constexpr (LPREC) raL = cvt4<LP>(cl.Ra[0], cl.Ra[1], cl.Ra[2], cl.Ra[3]);
+    if constexpr (ND && PREC > 0) {
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) rbL[kt] = cvt4<LP>(cl.Rb[kt][0], cl.Rb[kt][1], cl.Rb[kt][2], cl.Rb[kt][3]);
+    }
     yh[0] = recon(0, cl);
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
@@ -611,7 +627,6 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
       weights(t, ym, yh[t], wa[t], wb[t]);
       contract(t, cl, wa[t], wb[t]);
     }
-#if NNEF_SCHED
     // MFMA/VALU interleave: R(0); then per subtile its successor's R (KS
     // MFMAs) or its own ND (8 KT MFMAs) alternating with the weight VALU.
     __builtin_amdgcn_sched_group_barrier(0x008, LPREC ? 1 : KS, 0);
@@ -624,7 +639,6 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
         __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
       }
     }
-#endif
   };
 
   // ---- software pipeline: the HBM stream runs two steps ahead, the column
@@ -656,6 +670,10 @@ __device__ __forceinline__ void fused_pass_body(const FusedArgs& a, int braw, in
       for (int s = 0; s < KS; ++s) Lu[t][s] = 0.f;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) uN[kt] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (LPREC) {
+#pragma unroll
+      for (int t = 0; t < PT; ++t) LuL[t] = cvt4<LP>(0.f, 0.f, 0.f, 0.f);
+    }
   }
   YM ym0, ym1, ym2;
   Cols c0, c1, c2;

@@ -32,25 +32,32 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 // Reduced-precision contraction operands: MFMA m (0, 1) of the K = 16 form
 // takes this lane's accumulator rows v = 8m .. 8m+7 as its eight K slots; the
 // A and B operands use the same permutation of q, so the sum is unchanged.
-template <int PREC>
-__device__ __forceinline__ f16v mfma_lp(const float* av, const float* bv, const f16v& c) {
-  if constexpr (PREC == 1) {
-    bf16x8 x, y;
+// LP = 1: BF16, 2: FP16.  An operand is converted once and may feed several
+// MFMA (the column operand of N and D, the factor rows of every step of a qo).
+template <int LP>
+struct LpT {
+  typedef bf16x8 v8;
+};
+template <>
+struct LpT<2> {
+  typedef f16x8 v8;
+};
+
+template <int LP>
+__device__ __forceinline__ typename LpT<LP>::v8 cvt8(const float* v) {
+  typename LpT<LP>::v8 x;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      x[j] = (__bf16)av[j];
-      y[j] = (__bf16)bv[j];
-    }
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
-  } else {
-    f16x8 x, y;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      x[j] = (_Float16)av[j];
-      y[j] = (_Float16)bv[j];
-    }
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
+  for (int j = 0; j < 8; ++j) {
+    if constexpr (LP == 2) x[j] = (_Float16)v[j];
+    else x[j] = (__bf16)v[j];
   }
+  return x;
+}
+
+template <int LP>
+__device__ __forceinline__ f16v mfma8(const typename LpT<LP>::v8& a, const typename LpT<LP>::v8& b, const f16v& c) {
+  if constexpr (LP == 2) return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
 // PREC: input precision of the contractions: 0 = FP32; 1 = BF16, 2 = FP16
@@ -120,6 +127,7 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   // (reconstruction B operand), ul[t] = u[32t + c] (scales the contraction A
   // operand of kappa tile t, whose row is k = 32t + c)
   float Lu[NT][16];
+  typename LpT<(PREC > 2 ? PREC - 2 : 1)>::v8 LuL[NT][2];  // Lu converted once per qo (PREC > 2)
   float ul[NT];
   auto set_u = [&](int qo) {
     float uA[NT][16];
@@ -147,6 +155,13 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
         const float lv = (pval && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
         Lu[t][s] = lv * uA[t][s];
       }
+    if constexpr (PREC > 2) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        LuL[t][0] = cvt8<LP>(Lu[t]);
+        LuL[t][1] = cvt8<LP>(Lu[t] + 8);
+      }
+    }
   };
 
   // ---- column side of one step (raw inner rows).  Every load is a
@@ -295,8 +310,8 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
       // K = 16 form: MFMA m takes the lane's kappa values 8m .. 8m+7 of each tile
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        yh = mfma_lp<LP>(cl.Ra[t], Lu[t], yh);
-        yh = mfma_lp<LP>(cl.Ra[t] + 8, Lu[t] + 8, yh);
+        yh = mfma8<LP>(cvt8<LP>(cl.Ra[t]), LuL[t][0], yh);
+        yh = mfma8<LP>(cvt8<LP>(cl.Ra[t] + 8), LuL[t][1], yh);
       }
     } else {
 #pragma unroll
@@ -349,11 +364,12 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
             wav[v] = wa[v];
             wbv[v] = wb[v];
           }
-          accN[t] = mfma_lp<LP>(rb, wav, accN[t]);
-          accN[t] = mfma_lp<LP>(rb + 8, wav + 8, accN[t]);
+          const auto r0 = cvt8<LP>(rb), r1 = cvt8<LP>(rb + 8);
+          accN[t] = mfma8<LP>(r0, cvt8<LP>(wav), accN[t]);
+          accN[t] = mfma8<LP>(r1, cvt8<LP>(wav + 8), accN[t]);
           if (!a.no_d) {
-            accD[t] = mfma_lp<LP>(rb, wbv, accD[t]);
-            accD[t] = mfma_lp<LP>(rb + 8, wbv + 8, accD[t]);
+            accD[t] = mfma8<LP>(r0, cvt8<LP>(wbv), accD[t]);
+            accD[t] = mfma8<LP>(r1, cvt8<LP>(wbv + 8), accD[t]);
           }
         }
       }
@@ -393,6 +409,10 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
       for (int s = 0; s < 16; ++s) Lu[t][s] = 0.f;
+      if constexpr (PREC > 2) {
+        LuL[t][0] = cvt8<LP>(Lu[t]);
+        LuL[t][1] = cvt8<LP>(Lu[t] + 8);
+      }
       ul[t] = 1.f;
     }
   }
