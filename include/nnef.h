@@ -309,9 +309,13 @@ nnef_status nnef_step_learned(nnef_plan_t plan, nnef_mlp_t mlp, const float* Y,
  * width, loss, layout), with the restarts of a problem interleaved so that they
  * read each data tile at about the same time; one sweep over all runs is
  * captured in a hipGraph and replayed.  Tile sizes per width class are chosen
- * by nnef_batch_autotune.  Supported: models whose blocks need no materialised
- * side operand or chain-back contraction (CP-like strings such as
- * "ir,jr,kr,lr->ijkl"); others return NNEF_E_UNSUPPORTED.
+ * by nnef_batch_autotune.  CP-like strings (such as "ir,jr,kr,lr->ijkl") take
+ * the lowering without side operands; strings whose blocks need side operands
+ * or chain-back contractions (Tucker eq. 2.4, tensor train eq. 2.6, custom
+ * strings) run those contractions per run, in the captured sequence around the
+ * batched passes, each run with its own copy of its problem's workspace.
+ * Strings with no bilinear split (the direct lowering) return
+ * NNEF_E_UNSUPPORTED.
  * ------------------------------------------------------------------------ */
 typedef struct nnef_batch_s* nnef_batch_t;
 
@@ -327,7 +331,8 @@ typedef struct {
 } nnef_problem;
 
 /* Plan n_problems problems (options as for nnef_plan, shared).  Runs are
- * numbered problem-major, restart-minor.  Allocates per-run partial buffers. */
+ * numbered problem-major, restart-minor.  Allocates per-run partial buffers
+ * and, for problems with side operands, a per-run workspace. */
 nnef_status nnef_batch_plan(const nnef_problem* problems, int n_problems, const nnef_options* opt,
                             nnef_batch_t* out);
 void nnef_batch_destroy(nnef_batch_t batch);

@@ -148,7 +148,10 @@ static const char* prec_name(int prec, bool batched) {
 static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes, int n_modes,
                                const int64_t* ranks, int n_ranks, double alpha, double beta,
                                const nnef_options* opt, bool with_pack, int target_wg,
-                               nnef_plan_t* out, bool direct_only = false, bool dry_run = false) {
+                               nnef_plan_t* out, int batched = 0, bool dry_run = false) {
+  // batched: 0 = a single plan (bilinear lowering, else the direct one); 1 = a
+  // batched problem whose blocks need no side operands; 2 = a batched problem
+  // with side operands and chain-backs (no direct lowering in batched plans)
   if (!model_str || !out) return fail(NNEF_E_ARG, "model_str and out must not be NULL");
   *out = nullptr;
   auto* p = new nnef_plan_s();
@@ -216,8 +219,8 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
   size_t part_elems = 0;
   for (int l = 0; l < (int)m.ops.size(); ++l) {
     BlockPlan bp;
-    Status st = lower_block(m, l, bp, p->ws_sizes, err, direct_only);
-    if (st == ST_UNSUPPORTED && !direct_only) {  // no bilinear split: per-entry latent sums
+    Status st = lower_block(m, l, bp, p->ws_sizes, err, batched == 1);
+    if (st == ST_UNSUPPORTED && batched == 0) {  // no bilinear split: per-entry latent sums
       std::string err2;
       st = lower_direct(m, l, bp, p->ws_sizes, err2, target_wg);
       if (st != ST_OK) err += "; " + err2;
@@ -251,10 +254,10 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
   }
   if (dry_run) {  // lowering and geometry only: no device memory
     for (const auto& bp : p->blocks) {
-      // batched plans (direct_only) contract in FP32 at widths 16 and 64
-      const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!direct_only || bp.KP == 32);
+      // batched plans contract in FP32 at widths 16 and 64
+      const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!batched || bp.KP == 32);
       p->description += describe_block(m, bp) +
-                        (lp ? prec_name(p->opt.prec, direct_only) : " contract=fp32") +
+                        (lp ? prec_name(p->opt.prec, batched != 0) : " contract=fp32") +
                         "\n";
     }
     *out = p;
@@ -335,10 +338,10 @@ static nnef_status plan_create(const char* model_str, const int64_t* mode_sizes,
       free_plan(p);
       return st;
     }
-    // batched plans (direct_only) contract in FP32 at widths 16 and 64
-      const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!direct_only || bp.KP == 32);
+    // batched plans contract in FP32 at widths 16 and 64
+    const bool lp = !bp.direct && p->opt.prec != NNEF_FP32 && (!batched || bp.KP == 32);
     p->description += describe_block(m, bp) +
-                      (lp ? prec_name(p->opt.prec, direct_only) : " contract=fp32") + "\n";
+                      (lp ? prec_name(p->opt.prec, batched != 0) : " contract=fp32") + "\n";
   }
   if (hipDeviceSynchronize() != hipSuccess) {
     free_plan(p);
@@ -360,7 +363,7 @@ size_t nnef_plan_dry(const char* model_str, const int64_t* mode_sizes, int n_mod
                      char* buf, size_t buf_len) {
   nnef_plan_t p = nullptr;
   const nnef_status st = plan_create(model_str, mode_sizes, n_modes, ranks, n_ranks, alpha, beta, opt,
-                                     false, env_int("NNEF_TARGET_WG", 512), &p, false, true);
+                                     false, env_int("NNEF_TARGET_WG", 512), &p, 0, true);
   if (status) *status = st;
   if (st != NNEF_OK) return 0;
   const size_t n = nnef_plan_describe(p, buf, buf_len);
@@ -420,6 +423,20 @@ static int run_program(const nnef_plan_s* p, const BlockPlan& bp, const std::vec
   return 0;
 }
 
+// Two contractions that differ only in their operand and output pointers.
+static bool same_shape(const EinsumArgs& a, const EinsumArgs& b) {
+  bool same = a.n_in == b.n_in && a.n_out == b.n_out && a.n_sum == b.n_sum && a.n_out_total == b.n_out_total;
+  for (int d = 0; same && d < a.n_out; ++d) {
+    same = a.out_size[d] == b.out_size[d] && a.out_stride[d] == b.out_stride[d];
+    for (int j = 0; j < a.n_in; ++j) same = same && a.in_out_stride[j][d] == b.in_out_stride[j][d];
+  }
+  for (int d = 0; same && d < a.n_sum; ++d) {
+    same = a.sum_size[d] == b.sum_size[d];
+    for (int j = 0; j < a.n_in; ++j) same = same && a.in_sum_stride[j][d] == b.in_sum_stride[j][d];
+  }
+  return same;
+}
+
 // Two programs evaluated step by step together: the numerator and denominator
 // chains of a block, built alike from N_L and D_L, share each launch.
 static int run_program_pair(const nnef_plan_s* p, const BlockPlan& bp, const std::vector<Step>& pa,
@@ -431,15 +448,7 @@ static int run_program_pair(const nnef_plan_s* p, const BlockPlan& bp, const std
   for (size_t i = 0; i < pa.size(); ++i) {
     EinsumArgs a = einsum_args(p, bp, pa[i], factors);
     EinsumArgs b = einsum_args(p, bp, pb[i], factors);
-    bool same = a.n_in == b.n_in && a.n_out == b.n_out && a.n_sum == b.n_sum && a.n_out_total == b.n_out_total;
-    for (int d = 0; same && d < a.n_out; ++d) {
-      same = a.out_size[d] == b.out_size[d] && a.out_stride[d] == b.out_stride[d];
-      for (int j = 0; j < a.n_in; ++j) same = same && a.in_out_stride[j][d] == b.in_out_stride[j][d];
-    }
-    for (int d = 0; same && d < a.n_sum; ++d) {
-      same = a.sum_size[d] == b.sum_size[d];
-      for (int j = 0; j < a.n_in; ++j) same = same && a.in_sum_stride[j][d] == b.in_sum_stride[j][d];
-    }
+    const bool same = same_shape(a, b);
     const int e = same ? launch_einsum(a, s, &b) : launch_einsum(a, s);
     if (e) return e;
     if (!same) {
@@ -1126,6 +1135,15 @@ struct BatchBlock {
   int n_colsum = 0;
   WorkItem* d_uwork = nullptr;
   int n_uwork = 0;
+  // side operands before the pass and chain-backs after the update, for every
+  // run that needs them (each run has its own workspace)
+  std::vector<EinsumArgs> side;
+  struct Chain {
+    EinsumArgs n, d;
+    bool pair;
+  };
+  std::vector<Chain> chain;
+  std::vector<ApplyArgs> apply;
 };
 
 struct nnef_batch_s {
@@ -1135,6 +1153,7 @@ struct nnef_batch_s {
   int n_runs = 0, n_fac_ptrs = 0, L_max = 0;
   std::vector<float*> partN, partD, dcol;
   std::vector<double*> lpart;
+  std::vector<float*> run_ws;         // per run: a copy of its problem's workspace (or null)
   double* loss_slots = nullptr;       // [n_runs]
   std::vector<BatchBlock> blocks;
   int target[3] = {128, 128, 128};    // workgroups per run and pass, by width class 16/32/64
@@ -1170,6 +1189,9 @@ static void free_block_tables(BatchBlock& k) {
     if (q) (void)hipFree(q);
   k.d_colsum = nullptr;
   k.d_uwork = nullptr;
+  k.side.clear();
+  k.chain.clear();
+  k.apply.clear();
 }
 
 static void free_batch(nnef_batch_s* b) {
@@ -1180,6 +1202,8 @@ static void free_batch(nnef_batch_s* b) {
     for (float* q : *v)
       if (q) (void)hipFree(q);
   for (double* q : b->lpart)
+    if (q) (void)hipFree(q);
+  for (float* q : b->run_ws)
     if (q) (void)hipFree(q);
   if (b->loss_slots) (void)hipFree(b->loss_slots);
   for (auto* q : b->sub) free_plan(q);
@@ -1214,6 +1238,18 @@ static nnef_status upload(T** d, const std::vector<T>& h) {
 
 extern "C" {
 
+// Points a problem's workspace table at one run's copy while that run's
+// arguments are built (the lowering refers to buffers by index).
+struct WsBinding {
+  nnef_plan_s* q;
+  std::vector<float*> saved;
+  WsBinding(nnef_plan_s* q_, float* base) : q(q_), saved(q_->ws) {
+    if (base)
+      for (auto& w : q->ws) w = base + (w - (float*)q->ws_base);
+  }
+  ~WsBinding() { q->ws = saved; }
+};
+
 // Device argument and work tables for the given data and factor pointers.
 static nnef_status batch_tables(nnef_batch_s* b, const float* const* Y, const uint8_t* const* M,
                                 float* const* factors) {
@@ -1246,6 +1282,7 @@ static nnef_status batch_tables(nnef_batch_s* b, const float* const* Y, const ui
           for (int r = 0; r < nr; ++r) {
             const int run = run0 + r;
             float* const* fr = factors + b->run_fac[run];
+            WsBinding bind(q, b->run_ws[run]);
             FusedArgs a = fused_args(q, bp, Yd, msk, fr);
             // batched passes: widths 16 and 64 contract in FP32, the reconstruction stays FP32
             a.prec = bp.KP != 32 ? 0 : a.prec > 2 ? a.prec - 2 : a.prec;
@@ -1287,8 +1324,10 @@ static nnef_status batch_tables(nnef_batch_s* b, const float* const* Y, const ui
                 u.ldpiece[i] = bp.pieces[i].ld;
                 u.nrows[i] = bp.pieces[i].nrows;
               }
-              u.theta = fr[l];
+              u.theta = bp.L_direct ? fr[l] : nullptr;
               u.ldT = bp.ldL;
+              u.NL = bp.L_direct ? nullptr : q->ws[bp.NL_buf];
+              u.DL = bp.L_direct ? nullptr : q->ws[bp.DL_buf];
               u.upd = q->ls.upd;
               u.gamma = (float)q->ls.gamma;
               u.eps = (float)q->opt.eps;
@@ -1301,6 +1340,30 @@ static nnef_status batch_tables(nnef_batch_s* b, const float* const* Y, const ui
               if (a.no_d) colsum.push_back(run);
               const int nb = (int)((bp.nP * bp.K + 63) / 64);
               for (int j = 0; j < nb; ++j) uwork.push_back(WorkItem{run, j});
+              for (const Step& stp : bp.L_prog) k.side.push_back(einsum_args(q, bp, stp, fr));
+              for (const Step& stp : bp.R_prog) k.side.push_back(einsum_args(q, bp, stp, fr));
+              if (!bp.L_direct) {
+                std::vector<EinsumArgs> cn, cd;
+                for (const Step& stp : bp.chainN) cn.push_back(einsum_args(q, bp, stp, fr));
+                for (const Step& stp : bp.chainD) cd.push_back(einsum_args(q, bp, stp, fr));
+                bool pair = cn.size() == cd.size();
+                for (size_t i = 0; pair && i < cn.size(); ++i) pair = same_shape(cn[i], cd[i]);
+                if (pair) {
+                  for (size_t i = 0; i < cn.size(); ++i) k.chain.push_back(BatchBlock::Chain{cn[i], cd[i], true});
+                } else {  // the two chains one after the other
+                  for (const EinsumArgs& e : cn) k.chain.push_back(BatchBlock::Chain{e, e, false});
+                  for (const EinsumArgs& e : cd) k.chain.push_back(BatchBlock::Chain{e, e, false});
+                }
+                ApplyArgs aa;
+                aa.theta = fr[l];
+                aa.N = q->ws[bp.Nl_buf];
+                aa.D = q->ws[bp.Dl_buf];
+                aa.n = q->numel[l];
+                aa.upd = q->ls.upd;
+                aa.gamma = (float)q->ls.gamma;
+                aa.eps = (float)q->opt.eps;
+                k.apply.push_back(aa);
+              }
             }
           }
           for (int w = 0; w < bp.n_wg; ++w)
@@ -1343,6 +1406,10 @@ static nnef_status batch_sweep(nnef_batch_s* b, bool with_loss, hipStream_t s) {
   for (int l = 0; l < b->L_max; ++l) {
     BatchBlock& k = b->blocks[l];
     const int mode = (with_loss && l == 0) ? 1 : 0;
+    for (const EinsumArgs& e : k.side) {
+      const int ec = launch_einsum(e, s);
+      if (ec) return hip_fail(ec, "side-operand contraction launch");
+    }
     for (const BatchClass& c : k.cls[mode]) {
       BatchedLaunch L;
       L.args = k.d_fargs[mode];
@@ -1362,6 +1429,14 @@ static nnef_status batch_sweep(nnef_batch_s* b, bool with_loss, hipStream_t s) {
     const int e = launch_update_batched(k.d_uargs[mode], k.d_colsum, k.n_colsum, k.d_uwork, k.n_uwork,
                                         ugrid, s);
     if (e) return hip_fail(e, "batched update launch");
+    for (const BatchBlock::Chain& c : k.chain) {
+      const int ec = c.pair ? launch_einsum(c.n, s, &c.d) : launch_einsum(c.n, s);
+      if (ec) return hip_fail(ec, "chain-back contraction launch");
+    }
+    for (const ApplyArgs& a : k.apply) {
+      const int ec = launch_apply(a, s);
+      if (ec) return hip_fail(ec, "update launch");
+    }
   }
   return NNEF_OK;
 }
@@ -1378,20 +1453,18 @@ nnef_status nnef_batch_plan(const nnef_problem* probs, int n_problems, const nne
       return fail(NNEF_E_ARG, "n_restarts must be >= 1");
     }
     nnef_plan_t q = nullptr;
+    // CP-like strings keep the lowering without side operands; others (Tucker,
+    // tensor train, custom strings) take side operands and chain-backs
     nnef_status st = plan_create(d.model_str, d.mode_sizes, d.n_modes, d.ranks, d.n_ranks, d.alpha,
-                                 d.beta, opt, d.masked != 0, 128, &q, true);
+                                 d.beta, opt, d.masked != 0, 128, &q, 1);
+    if (st == NNEF_E_UNSUPPORTED)
+      st = plan_create(d.model_str, d.mode_sizes, d.n_modes, d.ranks, d.n_ranks, d.alpha, d.beta, opt,
+                       d.masked != 0, 128, &q, 2);
     if (st != NNEF_OK) {
       free_batch(b);
       return fail(st, "problem " + std::to_string(pi) + ": " + g_last_error);
     }
     b->sub.push_back(q);
-    for (const BlockPlan& bp : q->blocks)
-      if (!bp.L_direct || !bp.L_prog.empty() || !bp.R_prog.empty() || !bp.chainN.empty()) {
-        free_batch(b);
-        return fail(NNEF_E_UNSUPPORTED, "problem " + std::to_string(pi) +
-                                            ": batched plans take models whose blocks need no side "
-                                            "operands or chain-back (CP-like strings)");
-      }
     b->restarts.push_back(d.n_restarts);
     b->masked.push_back(d.masked != 0);
     const int L = (int)q->m.ops.size();
@@ -1423,17 +1496,23 @@ nnef_status nnef_batch_plan(const nnef_problem* probs, int n_problems, const nne
       free_batch(b);
       return fail(NNEF_E_SHAPE, "partial sums need 2^30 or more elements");
     }
+    size_t ws_total = 0;  // the problem's workspace, copied per run (with its initial contents)
+    for (auto v : q->ws_sizes) ws_total += (size_t)((v + 63) / 64 * 64);
     for (int r = 0; r < b->restarts[pi]; ++r) {
-      float *pn = nullptr, *pd = nullptr, *dc = nullptr;
+      float *pn = nullptr, *pd = nullptr, *dc = nullptr, *ws = nullptr;
       double* lp = nullptr;
       const bool ok = hipMalloc((void**)&pn, part * sizeof(float)) == hipSuccess &&
                       hipMalloc((void**)&pd, part * sizeof(float)) == hipSuccess &&
                       hipMalloc((void**)&dc, 64 * sizeof(float)) == hipSuccess &&
-                      hipMalloc((void**)&lp, wg * sizeof(double)) == hipSuccess;
+                      hipMalloc((void**)&lp, wg * sizeof(double)) == hipSuccess &&
+                      (ws_total == 0 ||
+                       (hipMalloc((void**)&ws, ws_total * sizeof(float)) == hipSuccess &&
+                        hipMemcpy(ws, q->ws_base, ws_total * sizeof(float), hipMemcpyDeviceToDevice) == hipSuccess));
       b->partN.push_back(pn);
       b->partD.push_back(pd);
       b->dcol.push_back(dc);
       b->lpart.push_back(lp);
+      b->run_ws.push_back(ws);
       if (!ok) {
         free_batch(b);
         return fail(NNEF_E_NOMEM, "per-run buffer allocation failed");

@@ -164,3 +164,50 @@ def test_full_size_batched_workload_sampled():
         ref = O.sweep("ir,jr,kr,lr->ijkl", [x.astype(np.float64) for x in before[(i, r)]], Y, None, 1.0, 0.0, EPS)
         got = [t.cpu().numpy() for t in runs[8 * i + r]]
         assert_step_parity(got, ref, TOL, f"problem {i} {desc[i]} restart {r}")
+
+
+def _side_problems():
+    """Strings whose blocks need side operands and chain-backs: Tucker (eq. 2.4,
+    masked IS), tensor train (eq. 2.6, masked KL), the ICEWS string (a grouped
+    column piece [a, r]) and NMF (a transposed operand), batched with a CP
+    problem; 1-3 restarts each."""
+    probs = [datagen.tucker3(I=30, J=26, K=18, Ra=6, Rb=5, Rc=4, seed=331),
+             datagen.tt4(I=13, J=11, K=9, Lm=7, Ra=3, Rb=4, Rc=5, seed=341),
+             datagen.poisson_problem("icews_b", "ir,jr,ak,kr,tr->ijat", dict(i=40, j=40, a=16, t=8, r=32, k=4),
+                                     1.0, 0.0, seed=351, truth_shape=0.5, missing=0.1),
+             datagen.poisson_problem("nmf_b", "ir,rj->ij", dict(i=50, j=37, r=8), 1.0, 0.0, seed=361,
+                                     truth_shape=0.5),
+             datagen.poisson_problem("cp_b", "ir,jr,kr->ijk", dict(i=21, j=19, k=17, r=12), 0.5, 1.0, seed=371,
+                                     truth_shape=0.5, missing=0.2)]
+    restarts = [3, 2, 1, 2, 1]
+    for i, (p, nr) in enumerate(zip(probs, restarts)):
+        p.init = [datagen.init_factors(p.model_str, p.sizes, 950 + 10 * i + r) for r in range(nr)]
+    return probs
+
+
+def test_batched_side_operands_match_oracle():
+    """Every run of a batch with side operands (per-run workspaces, chain-backs
+    in the captured sequence) matches the oracle's sweep at 1e-5, over three
+    calls (capture, then replays with eager work in between), and its loss
+    trace matches the oracle's loss of the state it belongs to."""
+    import torch
+    probs = _side_problems()
+    b = _batch(probs)
+    d = b.describe()
+    print(d, flush=True)
+    assert "chain-back" in d
+    Ys, Ms, runs = _device(probs)
+    facs = [f for _, f in runs]
+    for call in range(3):
+        before = [[t.cpu().numpy() for t in f] for f in facs]
+        tr = torch.zeros((1, b.n_runs), dtype=torch.float64, device="cuda")
+        b.step(Ys, Ms, facs, 1, loss_trace=tr if call == 2 else None)
+        torch.cuda.synchronize()
+        _check_runs(runs, before, f"side-operand call {call}")
+        if call == 2:
+            for r, (p, _) in enumerate(runs):
+                ref = O.loss(p.model_str, [x.astype(np.float64) for x in before[r]], p.Y, p.M, p.alpha, p.beta)
+                assert abs(tr[0, r].item() - ref) <= 1e-5 * ref, (r, tr[0, r].item(), ref)
+        plain = torch.ones(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert plain.item() == float(1 << 20)
