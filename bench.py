@@ -318,7 +318,7 @@ def bench_single(args):
         plan.step(Y, M, f, n_sweeps=args.steps)
         ev1.record()
         torch.cuda.synchronize()
-        plan.set_timing(True)  # per-pass durations from a second region (events slow the sweep)
+        plan.set_timing(True)  # per-pass durations from a second region
         plan.step(Y, M, f, n_sweeps=args.steps)
         torch.cuda.synchronize()
         n_pass, pass_ms = plan.timing()
@@ -424,9 +424,9 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     # per-launch durations of the fused pass: a second region of the same
-    # number of sweeps with an event pair around every pass on the plan's
-    # stream (the events themselves slow the sweep, so `value` comes from the
-    # region above, which has none)
+    # number of sweeps in which every pass is launched with an event pair that
+    # the launch records at the kernel's start and end on the plan's stream
+    # (`value` comes from the region above, which has no events)
     plan.set_timing(True)
     plan.step(Y, M, f, n_sweeps=args.steps)
     torch.cuda.synchronize()
@@ -445,8 +445,8 @@ def main():
               "alg_bytes_per_launch": alg_bytes, "alg_bytes_per_launch_uint8_mask": N * 5.0,
               "avg_launch_us": avg_pass_s * 1e6,
               "launches_timed": n_pass,
-              "launch_timing": "event pair around every fused pass over a second region of the same "
-                               "number of sweeps", "alg_TFLOPs": achieved, "alg_GBps": alg_bytes / avg_pass_s / 1e9}
+              "launch_timing": "start/end events recorded by every fused-pass launch (hipExtLaunchKernel) "
+                               "over a second region of the same number of sweeps", "alg_TFLOPs": achieved, "alg_GBps": alg_bytes / avg_pass_s / 1e9}
     if args.prec == "fp32":
         # 6 R flops per entry on FP32 MFMA: the contraction bounds the pass
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",

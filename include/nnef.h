@@ -188,12 +188,13 @@ nnef_status nnef_loss_device(nnef_plan_t plan, const float* Y, const uint8_t* ma
                              void* stream);
 
 /*
- * Kernel timing for measurement tools.  While enabled, nnef_step records a
- * hipEvent pair on `stream` around every fused pass (the pass over Y of each
- * block update).  nnef_plan_timing synchronises on those events and returns
- * the number of timed passes and their total duration in milliseconds, then
- * forgets them.  Disabled by default; enabling it adds two event records per
- * block update.
+ * Kernel timing for measurement tools.  While enabled, nnef_step launches
+ * every fused pass (the pass over Y of each block update) with a hipEvent
+ * pair that the launch itself records at the kernel's start and end
+ * (hipExtLaunchKernel), so the durations are those of the kernels.
+ * nnef_plan_timing synchronises on those events and returns the number of
+ * timed passes and their total duration in milliseconds, then forgets them.
+ * Disabled by default.
  */
 nnef_status nnef_plan_set_timing(nnef_plan_t plan, int enable);
 nnef_status nnef_plan_timing(nnef_plan_t plan, int* n_passes, double* total_ms);

@@ -582,10 +582,11 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
       fa.vloss_part = want_loss && vloss_slot ? p->vloss_part : nullptr;
     }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (p->timing) {
-      if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess ||
-          hipEventRecord(ev0, s) != hipSuccess)
+    if (p->timing) {  // recorded by the pass launch itself, at the kernel's start and end
+      if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
         return fail(NNEF_E_DEVICE, "timing event set-up failed");
+      g_pass_events.start = ev0;
+      g_pass_events.stop = ev1;
     }
     if (bp.direct) {
       DirectArgs da = direct_args(p, bp, Yd, masked, cf);
@@ -595,11 +596,16 @@ static nnef_status run_sweep(nnef_plan_s* p, const float* Yd, bool masked, float
     } else {
       e = launch_fused(fa, bp.KP, p->ls.wk, bp.vecq, want_loss ? 1 : 0, s);
     }
-    if (e) return hip_fail(e, "fused pass launch");
+    g_pass_events = PassEvents();
     if (p->timing) {
-      if (hipEventRecord(ev1, s) != hipSuccess) return fail(NNEF_E_DEVICE, "timing event record failed");
-      p->events.emplace_back(ev0, ev1);
+      if (e) {
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+      } else {
+        p->events.emplace_back(ev0, ev1);
+      }
     }
+    if (e) return hip_fail(e, "fused pass launch");
     UpdateArgs ua;
     std::memset(&ua, 0, sizeof(ua));
     ua.partN = p->partN;

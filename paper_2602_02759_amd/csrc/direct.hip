@@ -164,9 +164,9 @@ template <int WK, int MODE>
 int launch_direct_m(const DirectArgs& a, hipStream_t s) {
   const int grid = a.n_panels * a.n_chunks;
   if (a.K == 1)
-    hipLaunchKernelGGL((direct_pass<WK, MODE, 1>), dim3(grid), dim3(256), 0, s, a);
+    NNEF_LAUNCH_PASS((direct_pass<WK, MODE, 1>), dim3(grid), dim3(256), s, a);
   else
-    hipLaunchKernelGGL((direct_pass<WK, MODE, kDirectKPT>), dim3(grid), dim3(256), 0, s, a);
+    NNEF_LAUNCH_PASS((direct_pass<WK, MODE, kDirectKPT>), dim3(grid), dim3(256), s, a);
   return (int)hipGetLastError();
 }
 

@@ -21,11 +21,23 @@
 // one p: they feed the next MFMA directly as its B operand (K = q), with no
 // LDS round trip.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cfloat>
 #include <cmath>
 
 #include "nnef_internal.hpp"
+
+// A pass launch that records g_pass_events at the kernel's start and end when
+// they are set (see nnef_internal.hpp).
+#define NNEF_LAUNCH_PASS(kern, grid, block, stream, ...)                                            \
+  do {                                                                                             \
+    if (::nnef::g_pass_events.start)                                                               \
+      hipExtLaunchKernelGGL(kern, grid, block, 0, stream, (hipEvent_t)::nnef::g_pass_events.start, \
+                            (hipEvent_t)::nnef::g_pass_events.stop, 0, __VA_ARGS__);              \
+    else                                                                                           \
+      hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__);                               \
+  } while (0)
 
 namespace nnef {
 namespace {
@@ -753,9 +765,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 template <int KP, int WK, bool VECQ, int MODE, int PREC>
 int launch_fused_t(const FusedArgs& a, hipStream_t s) {
   if (a.full)
-    hipLaunchKernelGGL((fused_pass<KP, WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+    NNEF_LAUNCH_PASS((fused_pass<KP, WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), s, a);
   else
-    hipLaunchKernelGGL((fused_pass<KP, WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+    NNEF_LAUNCH_PASS((fused_pass<KP, WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), s, a);
   return (int)hipGetLastError();
 }
 

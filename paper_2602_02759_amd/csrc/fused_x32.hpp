@@ -594,9 +594,9 @@ fused_x32_batched(const FusedArgs* __restrict__ args, const WorkItem* __restrict
 template <int NT, int WK, bool VECQ, int MODE, int PREC>
 int launch_x32_p(const FusedArgs& a, hipStream_t s) {
   if (a.full)
-    hipLaunchKernelGGL((fused_x32<NT, WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+    NNEF_LAUNCH_PASS((fused_x32<NT, WK, VECQ, MODE, true, PREC>), dim3(a.n_wg), dim3(256), s, a);
   else
-    hipLaunchKernelGGL((fused_x32<NT, WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), 0, s, a);
+    NNEF_LAUNCH_PASS((fused_x32<NT, WK, VECQ, MODE, false, PREC>), dim3(a.n_wg), dim3(256), s, a);
   return (int)hipGetLastError();
 }
 

@@ -14,6 +14,8 @@
 
 namespace nnef {
 
+thread_local PassEvents g_pass_events;
+
 int launch_fused_kp16(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s);
 int launch_fused_kp32(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s);
 int launch_fused_kp64(const FusedArgs& a, int wk, bool vecq, int mode, hipStream_t s);

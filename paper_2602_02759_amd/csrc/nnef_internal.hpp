@@ -6,6 +6,16 @@
 
 namespace nnef {
 
+// Events (hipEvent_t) that the next fused or direct pass launch records at the
+// start and the end of the kernel itself (hipExtLaunchKernel), for per-pass
+// durations without the cost of separate event records; both null: an
+// ordinary launch.  Set by the host around one launch when timing is on.
+struct PassEvents {
+  void* start = nullptr;
+  void* stop = nullptr;
+};
+extern thread_local PassEvents g_pass_events;
+
 constexpr int kMaxPieces = 3;     // factors multiplied together to form one side row
 constexpr int kMaxEinsumIn = 4;   // inputs of one einsum step
 constexpr int kMaxEinsumLetters = 10;

@@ -55,6 +55,9 @@ def _case(name):
         return datagen.tucker3(I=301, J=301, K=64, Ra=32, Rb=32, Rc=16, seed=36)
     if name == "tt_small":
         return datagen.tt4(I=13, J=11, K=9, Lm=7, Ra=3, Rb=4, Rc=5, seed=41)
+    if name == "tt_two_sums":  # a chain-back summing two letters (j, and b of odd extent 9) that do
+        # not merge into one: lanes per output split the 810-term sum
+        return datagen.tt4(I=120, J=90, K=30, Lm=20, Ra=12, Rb=9, Rc=8, seed=44)
     if name == "tt_mid":
         return datagen.tt4(I=40, J=36, K=28, Lm=20, Ra=16, Rb=16, Rc=16, seed=42)
     if name == "cp4_r64":
@@ -153,7 +156,7 @@ SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_ge
          "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full",
          "lr_tucker", "lr_tucker_w32", "wits", "batched_side_gemm", "manybody_gen", "manybody_rank",
          "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is", "tucker_odd_sum", "icews_tall_r64",
-         "icews_grouped", "grouped_ija", "tucker_long_sum"]
+         "icews_grouped", "grouped_ija", "tucker_long_sum", "tt_two_sums"]
 DIRECT = {"manybody", "manybody_gen", "manybody_rank", "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is"}
 
 
