@@ -123,12 +123,56 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
   }
   double lsum = 0.0, vsum = 0.0;
 
-  // ---- per-qo state: Lu[t][s] = L[p][32t + 16g + s] * u[32t + 16g + s]
-  // (reconstruction B operand), ul[t] = u[32t + c] (scales the contraction A
-  // operand of kappa tile t, whose row is k = 32t + c)
-  float Lu[NT][16];
-  typename LpT<(PREC > 2 ? PREC - 2 : 1)>::v8 LuL[NT][2];  // Lu converted once per qo (PREC > 2)
-  float ul[NT];
+  // ---- row operand: Lr[t][s] = L[p][32t + 16g + s] (0 past K or the last
+  // row); loaded once in the ragged path, with each new qo for full tiles.
+  float Lr[NT][16];
+  auto load_L = [&]() {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int k = 32 * t + 16 * g + s;
+        Lr[t][s] = (pval && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
+      }
+  };
+
+  // ---- outer factors of a step's column index qo: u[k] = prod_m
+  // outer_m[orow_m[qo]][k].  In the ragged path their rows are moved into a
+  // per-wave LDS slot (qo mod 4) by direct-to-LDS loads that need no
+  // registers, one step ahead of the step that starts the qo, which reads
+  // them back: short inner modes start a new qo every few steps.
+  __shared__ float ulds[FULL ? 1 : 4][4][2 * KP];  // [wave][slot][piece * KP + k] (ragged path)
+  float* ub = &ulds[FULL ? 0 : wave][0][0];
+  const int nout = a.nouter;
+  auto dma_u = [&](int qo) {
+    if (nout == 0) return;
+    qo = __builtin_amdgcn_readfirstlane(qo);
+    const uint32_t r0 = a.orow[0][qo] * (uint32_t)a.ld_out[0];
+    const uint32_t r1 = nout > 1 ? a.orow[1][qo] * (uint32_t)a.ld_out[1] : r0;
+    const float* o1 = nout > 1 ? a.outer[1] : a.outer[0];
+    float* dst = ub + (qo & 3) * (2 * KP);
+    if constexpr (NT == 1) {  // lanes 0..31: piece 0, lanes 32..63: piece 1 (or piece 0 again)
+      const uint32_t e = (uint32_t)min(lane & 31, a.K - 1);
+      // the two row addresses as integers, selected per lane (no pointer array)
+      const uint64_t b0 = (uint64_t)(uintptr_t)(a.outer[0] + r0), b1 = (uint64_t)(uintptr_t)(o1 + r1);
+      const uint64_t src = (lane < 32 ? b0 : b1) + 4ull * e;
+      __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)src, (__attribute__((address_space(3))) void*)dst, 4,
+                                       0, 0);
+    } else {
+      const uint32_t e = (uint32_t)min(lane, a.K - 1);
+      __builtin_amdgcn_global_load_lds((const void*)(a.outer[0] + r0 + e),
+                                       (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(o1 + r1 + e),
+                                       (__attribute__((address_space(3))) void*)(dst + KP), 4, 0, 0);
+    }
+  };
+  // per-qo state, formed when a step starts a new qo: Lu[t][s] = L[p][32t +
+  // 16g + s] u[32t + 16g + s] (the reconstruction's B operand) and ul[t] =
+  // u[32t + c] (scales the contraction's A operand of kappa tile t).  Full
+  // tiles read the rows from memory there (their steps per qo are many);
+  // ragged tiles read the rows moved into LDS and the row operand Lr.
+  float Lu[NT][16], ul[NT];
+  typename LpT<(PREC > 2 ? PREC - 2 : 1)>::v8 LuL[NT][2];  // Lu converted (PREC > 2)
   auto set_u = [&](int qo) {
     float uA[NT][16];
 #pragma unroll
@@ -137,24 +181,48 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
       for (int s = 0; s < 16; ++s) uA[t][s] = 1.f;
       ul[t] = 1.f;
     }
-    for (int m = 0; m < a.nouter; ++m) {
-      const float* ob = a.outer[m];
-      const uint32_t roff = a.orow[m][qo] * (uint32_t)a.ld_out[m];
+    if constexpr (FULL) {
+      for (int m = 0; m < nout; ++m) {
+        const float* ob = a.outer[m];
+        const uint32_t roff = a.orow[m][qo] * (uint32_t)a.ld_out[m];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
+        for (int t = 0; t < NT; ++t) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) uA[t][s] *= ldf(ob, roff + min(32 * t + 16 * g + s, a.K - 1));
-        ul[t] *= ldf(ob, roff + min(32 * t + c, a.K - 1));
+          for (int s = 0; s < 16; ++s) uA[t][s] *= ldf(ob, roff + min(32 * t + 16 * g + s, a.K - 1));
+          ul[t] *= ldf(ob, roff + min(32 * t + c, a.K - 1));
+        }
       }
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int k = 32 * t + 16 * g + s;
+          const float lv = (pval && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
+          Lu[t][s] = lv * uA[t][s];
+        }
+    } else {
+      if (nout > 0) {
+        const float* us = ub + (qo & 3) * (2 * KP);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) uA[t][s] = us[32 * t + 16 * g + s];
+          ul[t] = us[32 * t + c];
+        }
+        if (nout > 1) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) uA[t][s] *= us[KP + 32 * t + 16 * g + s];
+            ul[t] *= us[KP + 32 * t + c];
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) Lu[t][s] = Lr[t][s] * uA[t][s];
     }
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int k = 32 * t + 16 * g + s;
-        const float lv = (pval && k < a.K) ? ldf(a.L, (uint32_t)p * (uint32_t)a.ldL + (uint32_t)k) : 0.f;
-        Lu[t][s] = lv * uA[t][s];
-      }
     if constexpr (PREC > 2) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -398,24 +466,11 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
       set_bases(lq);
     }
   };
-  int comp_qo = q0;
   if (nst > 0) {
+    if constexpr (!FULL) load_L();  // full tiles read their rows in set_u
     set_bases(q0);
-    // full tiles issue the first data moves before the factor rows below, so
-    // their latencies overlap (set_u runs inside the pipelined branch)
-    if constexpr (!FULL) set_u(q0);
-  } else {
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-      for (int s = 0; s < 16; ++s) Lu[t][s] = 0.f;
-      if constexpr (PREC > 2) {
-        LuL[t][0] = cvt8<LP>(Lu[t]);
-        LuL[t][1] = cvt8<LP>(Lu[t] + 8);
-      }
-      ul[t] = 1.f;
-    }
   }
+  int comp_qo = -1;  // qo whose Lu, ul are formed
   if constexpr (FULL) {
    if (nst > 0) {
     // Y: direct-to-LDS ring, kStages - 1 steps ahead; column side: registers,
@@ -452,6 +507,7 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
     load_cols(ibase, 32 * lqi, c0);
     if (nst > 1) adv_load();
     set_u(q0);
+    comp_qo = q0;
     auto stepf = [&](int64_t i, const Cols& cc, Cols& pc) {
       dma_ym(dybase, 32 * dqi, (int)((i + kStages - 1) % kStages));
       if (i + kStages < nst) adv_dma();
@@ -459,7 +515,7 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
       load_cols(ibase, 32 * lqi, pc);
       if (i + 2 < nst) adv_load();
       if (kq != comp_qo) {
-        if (a.nouter > 0) set_u(kq);
+        if (nout > 0) set_u(kq);
         comp_qo = kq;
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -481,22 +537,35 @@ __device__ __forceinline__ void fused_x32_body(const FusedArgs& a, int braw, int
    }
     __syncthreads();  // the ring memory is reused for the partial reduction
   } else {
+    // Outer-factor rows of a step are moved with the step's column and data
+    // loads, one step ahead; a step starts by waiting for everything issued
+    // so far (its own operands, which it needs anyway), then forms Lu, ul if
+    // it starts a new qo.
     YM y0, y1;
     Cols c0, c1;
+    int u_last = -1;  // qo whose rows were moved last
     if (nst > 0) {
       load_cols(ibase, 32 * lqi, c0);
       load_ym(ybase, 32 * lqi, y0);
+      dma_u(lq);
+      u_last = lq;
       if (nst > 1) adv_load();
     }
+    constexpr int kWait0 = (7 << 4) | (15 << 8);  // vmcnt(0)
     auto step = [&](int64_t i, const YM& cy, YM& py, const Cols& cc, Cols& pc) {
+      __builtin_amdgcn_s_waitcnt(kWait0);
+      if (kq != comp_qo) {
+        set_u(kq);
+        comp_qo = kq;
+      }
       if (i + 1 < nst) {
         load_cols(ibase, 32 * lqi, pc);
         load_ym(ybase, 32 * lqi, py);
+        if (lq != u_last) {
+          dma_u(lq);
+          u_last = lq;
+        }
         if (i + 2 < nst) adv_load();
-      }
-      if (kq != comp_qo) {
-        if (a.nouter > 0) set_u(kq);
-        comp_qo = kq;
       }
       compute(cy, cc);
       if (++kqi == a.nqis) {
