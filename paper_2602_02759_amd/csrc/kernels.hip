@@ -351,6 +351,40 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
         acc += (double)pr;
       }
     }
+  } else if (valid && a.n_sum == 2) {
+    // two summed letters, c = v0 * size1 + v1: the inner digit and the input
+    // offsets advance by G per term with at most one carry into the outer
+    // digit (G = g0 * size1 + g1, g1 < size1), so no division per term; the
+    // terms, products and grouping of the sums are those of the general path
+    const uint32_t s1 = (uint32_t)a.sum_size[1];
+    const uint32_t g0 = (uint32_t)G / s1, g1 = (uint32_t)G % s1;
+    uint32_t v1 = g % s1;
+    const int64_t v0 = (int64_t)(g / s1);
+    int64_t o[NIN], inc[NIN], wrap[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) {
+      const int64_t st0 = a.in_sum_stride[i][0], st1 = a.in_sum_stride[i][1];
+      o[i] = off[i] + v0 * st0 + (int64_t)v1 * st1;
+      inc[i] = (int64_t)g0 * st0 + (int64_t)g1 * st1;
+      wrap[i] = st0 - (int64_t)s1 * st1;
+    }
+    for (uint32_t c0 = g; c0 < n_sum; c0 += 4u * (uint32_t)G) {
+      float prod[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in_range = c0 + (uint32_t)u * (uint32_t)G < n_sum;
+        float pr = 1.f;
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) pr *= a.in[i][in_range ? o[i] : off[i]];
+        prod[u] = in_range ? pr : 0.f;
+        v1 += g1;
+        const bool carry = v1 >= s1;
+        v1 = carry ? v1 - s1 : v1;
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) o[i] += inc[i] + (carry ? wrap[i] : 0);
+      }
+      acc += ((double)prod[0] + (double)prod[1]) + ((double)prod[2] + (double)prod[3]);
+    }
   } else if (valid) {
     for (uint32_t c0 = g; c0 < n_sum; c0 += 4u * (uint32_t)G) {
       float prod[4];
