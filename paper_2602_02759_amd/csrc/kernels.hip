@@ -48,20 +48,40 @@ __device__ __forceinline__ float mu_rule(float th, float n, float d, int upd, fl
 }
 
 __device__ __forceinline__ void colsum_body(const UpdateArgs& a, float* dcol) {
-  // dcol[k] = prod_m sum_rows piece_m[row][k]; one workgroup, K <= 64
-  __shared__ double part[4][64];
-  const int k = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // dcol[k] = prod_m sum_rows piece_m[row][k]; one workgroup, K <= 64.  With
+  // KQ = K rounded up to a power of two, thread t takes column t % KQ and the
+  // rows t / KQ + j * (256 / KQ), four loads in flight; the row lanes of a
+  // column are then added in a fixed tree in LDS (deterministic).
+  __shared__ double part[256];
+  const int t = threadIdx.x;
+  int kq = 1;
+  while (kq < a.K) kq <<= 1;
+  const int k = t & (kq - 1), r0 = t / kq, rstep = 256 / kq;
   double prod = 1.0;
   for (int m = 0; m < a.npieces; ++m) {
-    double s = 0.0;
-    if (k < a.K)
-      for (int64_t row = w; row < a.nrows[m]; row += 4) s += a.piece[m][row * a.ldpiece[m] + k];
-    part[w][k] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (k < a.K) {
+      const float* col = a.piece[m] + k;
+      const int64_t ld = a.ldpiece[m], n = a.nrows[m];
+      int64_t row = r0;
+      for (; row + 3 * rstep < n; row += 4 * rstep) {
+        s0 += col[row * ld];
+        s1 += col[(row + rstep) * ld];
+        s2 += col[(row + 2 * rstep) * ld];
+        s3 += col[(row + 3 * rstep) * ld];
+      }
+      for (; row < n; row += rstep) s0 += col[row * ld];
+    }
+    part[t] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    if (w == 0) prod *= ((part[0][k] + part[1][k]) + part[2][k]) + part[3][k];
+    for (int h = rstep / 2; h > 0; h >>= 1) {
+      if (r0 < h) part[t] += part[t + h * kq];
+      __syncthreads();
+    }
+    if (t < kq) prod *= part[t];
     __syncthreads();
   }
-  if (w == 0 && k < a.K) dcol[k] = (float)prod;
+  if (t < a.K) dcol[t] = (float)prod;
 }
 
 __global__ __launch_bounds__(256) void colsum_kernel(UpdateArgs a, float* dcol) { colsum_body(a, dcol); }
