@@ -238,12 +238,25 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   if (i < a.n) a.theta[i] = mu_rule(a.theta[i], a.N[i], a.D[i], a.upd, a.gamma, a.eps);
 }
 
+// Operand and output pointers of a second contraction with the same shapes
+// (the denominator chain beside the numerator's): workgroups with
+// blockIdx.y = 1 take these.
+struct EinsumPtrs {
+  const float* in[kMaxEinsumIn];
+  float* out;
+};
+
 // One thread per output; NIN inputs (loops over inputs unrolled, offsets in
 // registers).  With no summed letter the output is a plain product.
 template <int NIN>
-__global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
+__global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a, EinsumPtrs b) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= a.n_out_total) return;
+  const bool second = blockIdx.y != 0;
+  const float* src[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) src[i] = second ? b.in[i] : a.in[i];
+  float* const dst = second ? b.out : a.out;
   int64_t off[NIN];
 #pragma unroll
   for (int i = 0; i < NIN; ++i) off[i] = 0;
@@ -271,8 +284,8 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
   if (a.n_sum == 0) {
     float prod = 1.f;
 #pragma unroll
-    for (int i = 0; i < NIN; ++i) prod *= a.in[i][off[i]];
-    a.out[ooff] = prod;
+    for (int i = 0; i < NIN; ++i) prod *= src[i][off[i]];
+    dst[ooff] = prod;
     return;
   }
   int64_t n_sum = 1;
@@ -282,7 +295,7 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
   for (int64_t cidx = 0; cidx < n_sum; ++cidx) {
     float prod = 1.f;
 #pragma unroll
-    for (int i = 0; i < NIN; ++i) prod *= a.in[i][off[i]];
+    for (int i = 0; i < NIN; ++i) prod *= src[i][off[i]];
     acc += (double)prod;
     for (int d = a.n_sum - 1; d >= 0; --d) {
       ++cnt[d];
@@ -294,7 +307,7 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
       cnt[d] = 0;
     }
   }
-  a.out[ooff] = (float)acc;
+  dst[ooff] = (float)acc;
 }
 
 // The same contraction with G lanes per output (G a power of two <= 64): lane
@@ -304,8 +317,14 @@ __global__ __launch_bounds__(256) void einsum_kernel(EinsumArgs a) {
 // few outputs with long sums, where one thread per output leaves the chip
 // idle and every thread waits on one load per term.
 template <int NIN, bool ONE_SUM>
-__global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log2g, uint32_t n_sum) {
+__global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, EinsumPtrs b, int log2g,
+                                                           uint32_t n_sum) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool second = blockIdx.y != 0;
+  const float* src[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) src[i] = second ? b.in[i] : a.in[i];
+  float* const dst = second ? b.out : a.out;
   const int G = 1 << log2g;
   const int64_t o = t >> log2g;
   const uint32_t g = (uint32_t)(t & (G - 1));
@@ -345,7 +364,7 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
 #pragma unroll
       for (int i = 0; i < NIN; ++i) {
         const int64_t st = a.in_sum_stride[i][0];
-        ptr[i] = a.in[i] + off[i] + (int64_t)g * st;
+        ptr[i] = src[i] + off[i] + (int64_t)g * st;
         step[i] = (int64_t)G * st;
       }
       uint32_t c = g;
@@ -395,7 +414,7 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
         const bool in_range = c0 + (uint32_t)u * (uint32_t)G < n_sum;
         float pr = 1.f;
 #pragma unroll
-        for (int i = 0; i < NIN; ++i) pr *= a.in[i][in_range ? o[i] : off[i]];
+        for (int i = 0; i < NIN; ++i) pr *= src[i][in_range ? o[i] : off[i]];
         prod[u] = in_range ? pr : 0.f;
         v1 += g1;
         const bool carry = v1 >= s1;
@@ -426,7 +445,7 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
           }
           float pr = 1.f;
 #pragma unroll
-          for (int i = 0; i < NIN; ++i) pr *= a.in[i][so[i]];
+          for (int i = 0; i < NIN; ++i) pr *= src[i][so[i]];
           prod[u] = pr;
         }
       }
@@ -434,7 +453,7 @@ __global__ __launch_bounds__(256) void einsum_split_kernel(EinsumArgs a, int log
     }
   }
   for (int m = G >> 1; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
-  if (valid && g == 0) a.out[ooff] = (float)acc;
+  if (valid && g == 0) dst[ooff] = (float)acc;
 }
 
 // Missing entries become -1 (observed data are nonnegative); the value stored
@@ -696,11 +715,11 @@ bool gemm_args(const EinsumArgs& e, GemmArgs& g) {
 }
 
 template <int NIN>
-void launch_split(const EinsumArgs& a, dim3 grid, int log2g, uint32_t n_sum, hipStream_t s) {
+void launch_split(const EinsumArgs& a, const EinsumPtrs& b, dim3 grid, int log2g, uint32_t n_sum, hipStream_t s) {
   if (a.n_sum == 1)
-    hipLaunchKernelGGL((einsum_split_kernel<NIN, true>), grid, dim3(256), 0, s, a, log2g, n_sum);
+    hipLaunchKernelGGL((einsum_split_kernel<NIN, true>), grid, dim3(256), 0, s, a, b, log2g, n_sum);
   else
-    hipLaunchKernelGGL((einsum_split_kernel<NIN, false>), grid, dim3(256), 0, s, a, log2g, n_sum);
+    hipLaunchKernelGGL((einsum_split_kernel<NIN, false>), grid, dim3(256), 0, s, a, b, log2g, n_sum);
 }
 
 // Two summed letters d, e whose strides satisfy stride(d) = size(e) * stride(e)
@@ -729,8 +748,8 @@ static EinsumArgs merge_sum_letters(EinsumArgs a) {
 }
 
 // Two contractions that differ only in their operand and output pointers
-// (the numerator and denominator chains of one block) go out as one launch
-// when they take the matrix-product form; otherwise one after the other.
+// (the numerator and denominator chains of one block) go out as one launch,
+// the second on blockIdx.y = 1.
 int launch_einsum(const EinsumArgs& a_in, void* stream, const EinsumArgs* second) {
   const EinsumArgs a = merge_sum_letters(a_in);
   if (a.n_out_total <= 0) return 0;
@@ -763,33 +782,35 @@ int launch_einsum(const EinsumArgs& a_in, void* stream, const EinsumArgs* second
       return (int)hipGetLastError();
     }
   }
-  if (second) {
-    const int e = launch_einsum(a_in, stream, nullptr);
-    return e ? e : launch_einsum(*second, stream, nullptr);
-  }
+  // otherwise the second contraction's pointers (same shapes, so the same
+  // merged letters) go out in the same launch as blockIdx.y = 1
+  EinsumPtrs b;
+  for (int i = 0; i < kMaxEinsumIn; ++i) b.in[i] = second ? second->in[i] : a.in[i];
+  b.out = second ? second->out : a.out;
+  const unsigned pairs = second ? 2u : 1u;
   if (n_sum >= 16 && n_sum < (int64_t(1) << 31) && a.n_in >= 1 && a.n_in <= 4) {
     // lanes per output: enough threads to fill the chip, at most 64
     int log2g = 0;
     while (log2g < 6 && (a.n_out_total << log2g) < (int64_t(1) << 19) && (int64_t(4) << log2g) < n_sum)
       ++log2g;
     const int64_t threads = a.n_out_total << log2g;
-    const dim3 grid((unsigned)((threads + 255) / 256));
+    const dim3 grid((unsigned)((threads + 255) / 256), pairs);
     hipStream_t s = (hipStream_t)stream;
     switch (a.n_in) {
-      case 1: launch_split<1>(a, grid, log2g, (uint32_t)n_sum, s); break;
-      case 2: launch_split<2>(a, grid, log2g, (uint32_t)n_sum, s); break;
-      case 3: launch_split<3>(a, grid, log2g, (uint32_t)n_sum, s); break;
-      default: launch_split<4>(a, grid, log2g, (uint32_t)n_sum, s); break;
+      case 1: launch_split<1>(a, b, grid, log2g, (uint32_t)n_sum, s); break;
+      case 2: launch_split<2>(a, b, grid, log2g, (uint32_t)n_sum, s); break;
+      case 3: launch_split<3>(a, b, grid, log2g, (uint32_t)n_sum, s); break;
+      default: launch_split<4>(a, b, grid, log2g, (uint32_t)n_sum, s); break;
     }
     return (int)hipGetLastError();
   }
-  const dim3 grid((unsigned)((a.n_out_total + 255) / 256));
+  const dim3 grid((unsigned)((a.n_out_total + 255) / 256), pairs);
   hipStream_t s = (hipStream_t)stream;
   switch (a.n_in) {
-    case 1: hipLaunchKernelGGL(einsum_kernel<1>, grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(einsum_kernel<2>, grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(einsum_kernel<3>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(einsum_kernel<4>, grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(einsum_kernel<1>, grid, dim3(256), 0, s, a, b); break;
+    case 2: hipLaunchKernelGGL(einsum_kernel<2>, grid, dim3(256), 0, s, a, b); break;
+    case 3: hipLaunchKernelGGL(einsum_kernel<3>, grid, dim3(256), 0, s, a, b); break;
+    default: hipLaunchKernelGGL(einsum_kernel<4>, grid, dim3(256), 0, s, a, b); break;
   }
   return (int)hipGetLastError();
 }
