@@ -166,9 +166,19 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const float* dc
 
 // Single plans: the waves per workgroup follow the number of partial slots,
 // so that every lane's loads are in flight at once (sixteen waves at the usual
-// 64 slots) and blocks with few slots (many rows) do not idle waves.
+// 64 slots) and blocks with few slots (many rows) do not idle waves.  With
+// the closed-form D and no dcol given, each 256-thread workgroup forms the
+// column sums itself in LDS (small outer pieces: one launch fewer).
 template <int NW, int U>
 __global__ __launch_bounds__(64 * NW) void update_kernel(UpdateArgs a, const float* dcol) {
+  if constexpr (NW == 4) {
+    __shared__ float dloc[64];
+    if (a.no_d && dcol == nullptr) {
+      colsum_body(a, dloc);
+      __syncthreads();
+      dcol = dloc;
+    }
+  }
   update_body<NW, U>(a, dcol, blockIdx.x);
 }
 
@@ -176,6 +186,12 @@ __global__ __launch_bounds__(64 * NW) void update_kernel(UpdateArgs a, const flo
 // summed in slot order; the first workgroup's first wave also finishes the
 // loss.
 __global__ __launch_bounds__(256) void update_flat_kernel(UpdateArgs a, const float* dcol) {
+  __shared__ float dloc[64];
+  if (a.no_d && dcol == nullptr) {
+    colsum_body(a, dloc);
+    __syncthreads();
+    dcol = dloc;
+  }
   const int64_t n = (int64_t)a.nP * a.K;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx < n) {
@@ -517,19 +533,25 @@ int launch_fused_batched(const BatchedLaunch& L, void* stream) {
 
 int launch_update(const UpdateArgs& a, float* dcol, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (a.no_d) {
+  // small outer pieces: the 256-thread update workgroups form the closed-form
+  // D themselves (a null dcol tells them to), saving the column-sum launch
+  int64_t piece_elems = 0;
+  for (int m = 0; m < a.npieces; ++m) piece_elems += a.nrows[m] * a.K;
+  const bool inline_d = a.no_d && a.n_chunks < 32 && piece_elems <= 65536;
+  if (a.no_d && !inline_d) {
     hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, a, dcol);
   }
+  const float* dc = inline_d ? nullptr : dcol;
   const int64_t n = (int64_t)a.nP * a.K;
   const int grid = (int)((n + 63) / 64);
   const dim3 g(grid > 0 ? grid : 1);
   if (a.n_chunks >= 32)
-    hipLaunchKernelGGL((update_kernel<16, 4>), g, dim3(1024), 0, s, a, dcol);
+    hipLaunchKernelGGL((update_kernel<16, 4>), g, dim3(1024), 0, s, a, dc);
   else if (a.n_chunks >= 4)
-    hipLaunchKernelGGL((update_kernel<4, 8>), g, dim3(256), 0, s, a, dcol);
+    hipLaunchKernelGGL((update_kernel<4, 8>), g, dim3(256), 0, s, a, dc);
   else
     hipLaunchKernelGGL(update_flat_kernel, dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)), dim3(256), 0, s, a,
-                       dcol);
+                       dc);
   return (int)hipGetLastError();
 }
 
