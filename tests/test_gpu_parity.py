@@ -37,6 +37,9 @@ def _case(name):
         return datagen.cp3(0.7, 0.3, sizes=dict(i=37, j=29, k=23), R=5, seed=24)
     if name == "cp3_ragged_euc_nomask":  # padded tile entries must count as missing
         return datagen.cp3(1.0, 1.0, sizes=dict(i=37, j=29, k=23), R=27, seed=27, missing=0.0)
+    if name == "cp3_kl_nomask_long":  # closed-form D both ways: block i forms it inside its update
+        # workgroups (11 partial slots), blocks j and k take the column-sum launch (200 slots)
+        return datagen.cp3(1.0, 0.0, sizes=dict(i=1200, j=64, k=64), R=32, seed=28, missing=0.0)
     if name == "tucker_is_nomask":
         return datagen.tucker3(I=30, J=26, K=18, Ra=6, Rb=5, Rc=4, seed=33, missing=0.0)
     if name == "cp3_full_euc":
@@ -156,7 +159,7 @@ SMALL = ["nmf", "cp3_small_euc", "cp3_small_ab", "cp3_ragged_kl", "cp3_ragged_ge
          "hellinger", "is", "shared_letter", "cp3_ragged_euc_nomask", "tucker_is_nomask", "icews_tall", "icews_tall_full",
          "lr_tucker", "lr_tucker_w32", "wits", "batched_side_gemm", "manybody_gen", "manybody_rank",
          "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is", "tucker_odd_sum", "icews_tall_r64",
-         "icews_grouped", "grouped_ija", "tucker_long_sum", "tt_two_sums"]
+         "icews_grouped", "grouped_ija", "tucker_long_sum", "tt_two_sums", "cp3_kl_nomask_long"]
 DIRECT = {"manybody", "manybody_gen", "manybody_rank", "permuted_direct", "row_scaling", "cp_r70", "cp_r96_is"}
 
 
